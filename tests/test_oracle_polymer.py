@@ -1,0 +1,93 @@
+"""Pins the oracle's bead-spring polymer (Eq. 7 with the LJ cut-and-shift
+and FENE parameters of the polymer workload): closed-form pair energies,
+running-energy bookkeeping, and the stationary bond-length distribution of a
+dimer under fixed bin weights, integrated exactly."""
+import math
+
+import numpy as np
+import pytest
+
+from synth import polymer_walk
+
+SHIFT = 4.0 * (2.5 ** -12 - 2.5 ** -6)
+
+
+def make(orc, pos, **kw):
+    C, N, _ = pos.shape
+    return orc.PolymerRun(n_beads=N, n_chains=C, seed=kw.pop("seed", 5), pos=pos, **kw)
+
+
+def test_pair_energies_closed_form(orc):
+    r = make(orc, polymer_walk(3, 1, 0))
+    # dimer at the FENE rest length
+    assert r.energy(np.array([[0, 0, 0], [1, 0, 0]], np.float32)) == 0.0
+    e = r.energy(np.array([[0, 0, 0], [1.25, 0, 0]], np.float32))
+    assert abs(e - (-5.0 * math.log(1 - 0.25))) < 1e-12
+    assert r.energy(np.array([[0, 0, 0], [1.5, 0, 0]], np.float32)) == math.inf
+    # trimer straight: LJ between the ends at r = 2, shifted
+    e = r.energy(np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0]], np.float32))
+    assert abs(e - (4 * (2.0 ** -12 - 2.0 ** -6) - SHIFT)) < 1e-12
+    # ends at r = 1 (sigma): LJ = -shift = +0.016317
+    h = math.sqrt(0.75)
+    e = r.energy(np.array([[0, 0, 0], [0.5, h, 0], [1, 0, 0]], np.float32))
+    x = np.array([[0, 0, 0], [0.5, h, 0], [1, 0, 0]], np.float32).astype(float)
+    fb = [np.linalg.norm(x[1] - x[0]), np.linalg.norm(x[2] - x[1])]
+    fene = sum(-5.0 * math.log(1 - ((b - 1) / 0.5) ** 2) for b in fb)
+    assert abs(e - (fene - SHIFT)) < 1e-9 and abs(-SHIFT - 0.016316891) < 1e-9
+    # beyond the cutoff
+    e = r.energy(np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [2, 1.6, 0]], np.float32))
+    assert np.isfinite(e)
+
+
+def test_lj_minimum(orc):
+    r = make(orc, polymer_walk(3, 1, 0))
+    rm = 2 ** (1 / 6)
+    best = min(r.energy(np.array([[0, 0, 0], [0.5 * d, math.sqrt(1 - 0.25 * d * d), 0], [d, 0, 0]],
+                                 np.float32)) for d in np.linspace(1.0, 1.3, 301))
+    # the two bonds stay at r0 (FENE 0) while the ends scan through the LJ well
+    assert abs(best - (-1.0 - SHIFT)) < 1e-3
+    assert abs(rm - 1.122462) < 1e-6
+
+
+def test_initial_walk_and_running_energy(orc):
+    pos = polymer_walk(40, 6, 5)
+    r = make(orc, pos)
+    assert np.all((r.E > -200) & (r.E < 50))
+    r.lnW = -0.5 * r.bin_centres()        # canonical-like weights so moves mix
+    r.sweeps(200, record=False)
+    r.advance(200)
+    for c in range(6):
+        e = r.energy(r.pos[c])
+        assert abs(e - r.E[c]) < 1e-9
+        assert r.bin[c] == r.bin_of(r.E[c])
+    assert not np.array_equal(r.pos, pos)
+
+
+def test_dimer_bond_length_distribution(orc):
+    """Two beads: the relative vector is uniform in space times the weight of
+    the energy bin, so H_b is proportional to exp(lnW_b) times the integral
+    of r^2 dr over the r with U_FENE(r) in bin b (U symmetric about r0)."""
+    beta = 1.0
+    C = 128
+    pos = np.zeros((C, 2, 3), np.float32)
+    pos[:, 1, 0] = 1.0
+    r = make(orc, pos, seed=9)
+    cent = r.bin_centres()
+    r.lnW = -beta * cent
+    r.sweeps(200, record=False)
+    r.advance(200)
+    H = r.sweeps(6000).astype(float)
+    edges = -200.0 + 0.1 * np.arange(r.n_bins + 1)
+
+    def cube_span(E):  # integral of r^2 over |r-1| <= 0.5 sqrt(1-exp(-E/5))
+        a = 0.5 * np.sqrt(1 - np.exp(-np.clip(E, 0, None) / 5.0))
+        return ((1 + a) ** 3 - (1 - a) ** 3) / 3
+
+    w = (cube_span(edges[1:]) - cube_span(edges[:-1])) * np.exp(-beta * cent)
+    # compare in windows of one energy unit
+    sel = slice(2000, 2060)
+    Hw = H[sel].reshape(-1, 10).sum(1)
+    ww = w[sel].reshape(-1, 10).sum(1)
+    assert H[:2000].sum() == 0
+    ratio = (Hw / Hw.sum()) / (ww / ww.sum())
+    assert np.abs(ratio[:3] - 1).max() < 0.03, ratio
