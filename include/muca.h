@@ -1,0 +1,181 @@
+/*
+ * muca.h -- C ABI of the MI355X (gfx950) parallel multicanonical library.
+ *
+ * Method: Zierenberg, Marenz, Janke, "Scaling Properties of Parallelized
+ * Multicanonical Simulations" (arXiv:1312.2213).  p independent Markov
+ * chains share one weight function W; after each iteration their histograms
+ * are merged into H^(n) and the next weights W^(n+1) are computed from all
+ * statistics gathered so far (parallel-scheme paragraph, Fig. 1 caption).
+ *
+ * Conventions for every entry point:
+ *  - Return value: MUCA_OK (0) on success, a negative muca_status otherwise;
+ *    no exception crosses the ABI.  muca_last_error() returns a thread-local
+ *    message for the last failure on the calling thread.
+ *  - On MUCA_E_ARG / MUCA_E_RANGE / MUCA_E_NOMEM the run is left unchanged.
+ *    On MUCA_E_HIP the run is poisoned and later calls return MUCA_E_STATE.
+ *  - Pointers named d_* are device (HBM) pointers, h_* are host pointers.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - The library never allocates or frees device memory: the caller passes a
+ *    device workspace of muca_workspace_bytes() bytes (256-byte aligned) and
+ *    keeps it, and the stream, alive until muca_free().  Host-side state
+ *    (log weights, accumulated statistics, a mirror of the thresholds) is
+ *    owned by the run handle.
+ *  - A run is used from one thread at a time; distinct runs are independent.
+ */
+#ifndef MUCA_H
+#define MUCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MUCA_ABI_VERSION 1u
+
+typedef enum muca_status {
+    MUCA_OK = 0,
+    MUCA_E_ARG = -1,   /* invalid argument or configuration              */
+    MUCA_E_NOMEM = -2, /* workspace too small                            */
+    MUCA_E_HIP = -3,   /* a HIP runtime call failed (run poisoned)       */
+    MUCA_E_STATE = -4, /* call out of order, or run poisoned             */
+    MUCA_E_RANGE = -5  /* a chain is outside the binned range            */
+} muca_status;
+
+/* Models (paper: Ising and Potts paragraphs, Eq. 3 for MUMA, Eq. 7 for the
+ * polymer). */
+typedef enum muca_model {
+    MUCA_ISING = 0,  /* 2D Ising, H = -sum s_i s_j (J = 1); bins over E       */
+    MUCA_POTTS = 1,  /* 2D q-state Potts; bins over E_unsat (unsatisfied bonds) */
+    MUCA_MUMA = 2,   /* 2D Ising at fixed beta, weight W(M) (Eq. 3); bins over M */
+    MUCA_POLYMER = 3 /* bead-spring homopolymer, LJ + FENE (Eq. 7); bins over E */
+} muca_model;
+
+/* Lattice storage in HBM; results never depend on it. */
+typedef enum muca_layout {
+    MUCA_LAYOUT_AUTO = 0,
+    MUCA_LAYOUT_BIT = 1, /* Ising/MUMA: one bit per spin                     */
+    MUCA_LAYOUT_BYTE = 2 /* Ising/MUMA: int8 +-1; Potts: uint8 colour       */
+} muca_layout;
+
+typedef struct muca_config {
+    uint32_t abi_version;   /* must be MUCA_ABI_VERSION                        */
+    int32_t model;          /* muca_model                                      */
+    int32_t L;              /* lattice: periodic L x L, L in {4,8,16,24,32,48,64} */
+    int32_t q;              /* Potts: 2..255                                   */
+    int32_t n_chains;       /* p, number of independent realisations (>= 1)   */
+    int32_t layout;         /* muca_layout                                     */
+    uint64_t seed;          /* Philox key                                      */
+    int32_t lo, hi;         /* lattice: inclusive binned range, in units of the
+                               binned quantity (Ising E step 4, Potts E_unsat
+                               step 1, MUMA M step 2)                          */
+    double beta;            /* MUMA: fixed inverse temperature                 */
+    double flat_threshold;  /* flat iff min(H)/mean(H) over the flatness set > this */
+    int32_t chains_per_block; /* 0 = auto, else 64, 128 or 256               */
+    int32_t table_in_lds;   /* -1 auto, 0 thresholds read from global memory, 1 staged in LDS */
+    /* polymer */
+    int32_t n_beads;        /* 2..64                                           */
+    int32_t n_bins;         /* energy bins on [x_lo, x_hi)                     */
+    double x_lo, x_hi;
+    double lj_eps, lj_sigma, lj_rcut;
+    double fene_k, fene_r0, fene_R; /* FENE -(K/2) R^2 ln(1-((r-r0)/R)^2)     */
+    float step;             /* side of the displacement cube                   */
+    int32_t reserved;
+} muca_config;
+
+typedef struct muca_iter_stats {
+    int64_t iteration;  /* n of the merged histogram H^(n), from 0             */
+    int64_t sweeps;     /* sweeps per chain that went into H^(n)               */
+    int64_t samples;    /* sum of H^(n)                                        */
+    double flatness;    /* min/mean of H^(n) over the flatness set             */
+    int32_t flat;       /* flatness > flat_threshold                           */
+    int32_t lo_visited; /* lowest / highest bin with H^(n) > 0, -1 if none     */
+    int32_t hi_visited;
+    int32_t reserved;
+} muca_iter_stats;
+
+typedef struct muca_run muca_run;
+
+/* Fills *cfg with defaults for the model: full binned range, layout AUTO,
+ * flat_threshold 0.5, polymer parameters of the bead-spring workload (LJ
+ * eps = sigma = 1 cut at 2.5 and shifted; FENE K = 40, r0 = 1, R = 0.5;
+ * 2500 bins on [-200, 50); step 0.3). */
+int muca_config_default(int32_t model, int32_t L, int32_t q, int32_t n_chains, uint64_t seed,
+                        muca_config *cfg);
+
+/* Device workspace needed by muca_init for this configuration. */
+int muca_workspace_bytes(const muca_config *cfg, uint64_t *bytes);
+
+/* Initialises p realisations with the same weights lnW = 0 (parallel-scheme
+ * paragraph).  Lattices: spins drawn on the device from the Philox stream
+ * (chain, 0, site/4, INIT); then E, M and the bins.  Polymer:
+ * h_positions = [n_chains][n_beads][3] float conformations (host), copied.
+ * Enqueued on `stream` and synchronised before returning.  MUCA_E_RANGE if a
+ * chain starts outside the binned range. */
+int muca_init(const muca_config *cfg, void *d_workspace, uint64_t workspace_bytes,
+              const float *h_positions, void *stream, muca_run **out);
+
+/* Enqueues `sweeps` sweeps of every chain with the current thresholds,
+ * accumulating into the device histogram (asynchronous).  Repeated calls
+ * before muca_merge_update extend the same iteration.  A sweep visits the
+ * sites in row-major order (polymer: beads 0..N-1); after each sweep every
+ * chain adds one entry to H.  Metropolis acceptance min(1, W(E')/W(E))
+ * (MUMA: min(1, exp(-beta dE) W(M')/W(M))) by integer thresholds. */
+int muca_run_iteration(muca_run *run, int64_t sweeps, void *stream);
+
+/* Same, but the sweeps are not histogrammed (thermalisation). */
+int muca_thermalize(muca_run *run, int64_t sweeps, void *stream);
+
+/* Ends iteration n: waits for the run's stream, merges H^(n), evaluates
+ * flatness, applies the accumulated-statistics recursion in FP64 to obtain
+ * lnW^(n+1), builds and uploads the new thresholds, clears H.  MUCA_E_STATE
+ * if no sweeps were enqueued since the last merge. */
+int muca_merge_update(muca_run *run, muca_iter_stats *out);
+
+/* Reweighting (Eq. 2) of the last merged pair (H^(n), lnW^(n)).
+ * Energy ensembles: for each beta[k], out[4k..4k+3] = { <E>/N, beta^2
+ * Var(E)/N, <E>, ln sum_b H_b W_b^-1 e^(-beta E_b) } with N sites (beads).
+ * MUMA (canonical at the run's beta; pass n = 1, betas may be NULL):
+ * out = { <|M|>/N, <M^2>/N^2, <M>/N, ln sum_b H_b W_b^-1 }.
+ * Potts energies are E_unsat - 2N; polymer bins use their centres. */
+int muca_reweight(const muca_run *run, const double *betas, int32_t n, double *out);
+
+/* One persistent launch for several runs (mixed models, L, q, ensembles):
+ * equivalent to muca_run_iteration(runs[i], sweeps[i]) for every i, with
+ * identical results.  d_batch_ws is caller-owned device memory of
+ * muca_batch_workspace_bytes(n) bytes.  When graph != 0 the launch is
+ * captured once in a hipGraph and relaunched on later calls with the same
+ * runs. */
+int muca_batch_workspace_bytes(int32_t n_runs, uint64_t *bytes);
+int muca_batch_run_iteration(muca_run *const *runs, int32_t n_runs, const int64_t *sweeps,
+                             void *d_batch_ws, uint64_t batch_ws_bytes, int32_t graph, void *stream);
+
+/* Accessors (host copies; synchronise the run's stream). */
+int muca_sizes(const muca_run *run, int32_t *n_bins, int32_t *n_cols, int32_t *n_sites);
+int muca_get_lnw(const muca_run *run, double *h_lnw, int32_t n_bins);
+int muca_get_last_hist(const muca_run *run, uint64_t *h_hist, int32_t n_bins);
+int muca_get_thresholds(const muca_run *run, uint32_t *h_t, int64_t count);
+/* Lattice: spins[count][N] int8 (Ising/MUMA +-1, Potts colour), bins[count].
+ * Polymer: positions[count][n_beads][3] float into `state`, energies[count]
+ * double into `energy`.  Either output may be NULL. */
+int muca_get_chain_state(const muca_run *run, int32_t chain0, int32_t count, void *state,
+                         int32_t *bins, double *energy);
+
+/* Test hooks: replace lnW (thresholds rebuilt) or the thresholds themselves
+ * (count = n_bins * n_cols; polymer n_bins^2). */
+int muca_set_lnw(muca_run *run, const double *h_lnw, int32_t n_bins);
+int muca_set_thresholds(muca_run *run, const uint32_t *h_t, int64_t count);
+
+/* Checkpoint / restore of the complete run state (chains, sweep counter,
+ * weights, accumulated statistics).  muca_checkpoint with h_buf = NULL
+ * returns the size in *bytes. */
+int muca_checkpoint(const muca_run *run, void *h_buf, uint64_t *bytes);
+int muca_restore(muca_run *run, const void *h_buf, uint64_t bytes);
+
+void muca_free(muca_run *run);
+const char *muca_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MUCA_H */

@@ -1,0 +1,52 @@
+// muca_internal.h -- structures shared by the host runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace muca {
+
+enum Model : int32_t { kIsing = 0, kPotts = 1, kMuma = 2, kPolymer = 3 };
+enum Layout : int32_t { kLayoutBit = 1, kLayoutByte = 2 };
+
+// Arguments of one lattice sweep launch.  Lattice words are interleaved
+// across chains: word w of row y of chain c lives at
+// words[(y * wpr + w) * c_pad + c], so a wavefront's 64 lanes touch 64
+// consecutive 32-bit words.
+struct LatticeArgs {
+    uint32_t *words;            // [L * wpr][c_pad]
+    int32_t *bins;              // [c_pad] current bin of each chain
+    const uint32_t *thresholds; // [n_bins * n_cols]
+    unsigned long long *hist;   // [n_bins]
+    uint32_t k0, k1;            // Philox key (seed)
+    uint32_t g0;                // global sweep id of the first sweep
+    int32_t n_sweeps;
+    int32_t n_chains;           // chains >= n_chains are padding: never histogrammed
+    int32_t c_pad;
+    int32_t n_bins;
+    int32_t q;
+    int32_t record;             // histogram the sweeps
+    int32_t table_in_lds;
+    int32_t chain0;             // global index of the first chain handled
+};
+
+struct LatticeInitArgs {
+    uint32_t *words;
+    int32_t *bins;
+    int32_t *values; // [c_pad] E (Ising/Potts E_unsat) or M (MUMA) after init
+    uint32_t k0, k1;
+    int32_t c_pad;
+    int32_t L, q, lo, step;
+    int32_t model, layout;
+};
+
+// Number of 32-bit words per lattice row.
+__host__ __device__ inline int words_per_row(int L, int layout) { return layout == kLayoutBit ? (L + 31) / 32 : (L + 3) / 4; }
+
+// Launchers (lattice.hip).
+hipError_t launch_lattice_init(const LatticeInitArgs &a, hipStream_t s);
+hipError_t launch_lattice_sweeps(int model, int L, int layout, int chains_per_block, int n_cols,
+                                 const LatticeArgs &a, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t s);
+bool lattice_size_supported(int L);
+
+} // namespace muca

@@ -1,0 +1,895 @@
+// runtime.cpp -- host side of the C ABI (include/muca.h).
+//
+// Owns the per-run host state of the multicanonical iteration
+// (arXiv:1312.2213, parallel-scheme paragraph and Fig. 1 caption):
+//   * the log weights lnW and, for the recursion that uses the statistics of
+//     all earlier iterations (paragraph after Eq. 2), the log weight ratios
+//     lnR of neighbouring bins and their accumulated statistical weights P;
+//   * the flatness test that ends the iteration;
+//   * the integer acceptance thresholds uploaded for the kernels;
+//   * reweighting to canonical averages (Eq. 2).
+// All FP64 arithmetic here runs in a fixed order (no FMA contraction), so
+// the weights and thresholds are reproducible bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/muca.h"
+#include "muca_internal.h"
+#include "runtime_internal.h"
+
+using namespace muca;
+
+static thread_local std::string g_last_error;
+
+int muca_fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+const char *muca_last_error(void) { return g_last_error.c_str(); }
+
+#define HIP_OR_POISON(run, expr)                                                                   \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) {                                                                    \
+            (run)->poisoned = true;                                                                \
+            return muca_fail(MUCA_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));                  \
+        }                                                                                          \
+    } while (0)
+
+static size_t align256(size_t x) { return (x + 255u) & ~(size_t)255u; }
+
+// ---------------------------------------------------------------------------
+// Geometry of a configuration
+// ---------------------------------------------------------------------------
+static int bin_step(int model) { return model == kIsing ? 4 : (model == kPotts ? 1 : 2); }
+
+static int n_cols_of(int model) { return model == kIsing ? 5 : (model == kPotts ? 9 : 10); }
+
+int muca_geometry(const muca_config *c, Geometry *g)
+{
+    if (!c || !g)
+        return muca_fail(MUCA_E_ARG, "null argument");
+    if (c->abi_version != MUCA_ABI_VERSION)
+        return muca_fail(MUCA_E_ARG, "abi_version %u, library has %u", c->abi_version, MUCA_ABI_VERSION);
+    if (c->n_chains < 1)
+        return muca_fail(MUCA_E_ARG, "n_chains must be >= 1");
+    std::memset(g, 0, sizeof *g);
+    g->model = c->model;
+    g->c_pad = (c->n_chains + 63) / 64 * 64;
+    if (c->model == kPolymer)
+        return muca_polymer_geometry(c, g);
+    if (c->model != kIsing && c->model != kPotts && c->model != kMuma)
+        return muca_fail(MUCA_E_ARG, "unknown model %d", c->model);
+    if (!lattice_size_supported(c->L))
+        return muca_fail(MUCA_E_ARG, "L = %d not compiled (4, 8, 16, 24, 32, 48, 64)", c->L);
+    const int N = c->L * c->L;
+    g->L = c->L;
+    g->n_sites = N;
+    g->step = bin_step(c->model);
+    g->n_cols = n_cols_of(c->model);
+    if (c->model == kPotts) {
+        if (c->q < 2 || c->q > 255)
+            return muca_fail(MUCA_E_ARG, "q = %d outside 2..255", c->q);
+        if (c->lo < 0 || c->hi > 2 * N || c->lo > c->hi)
+            return muca_fail(MUCA_E_ARG, "Potts range [%d, %d] outside [0, %d]", c->lo, c->hi, 2 * N);
+        g->layout = kLayoutByte;
+    } else {
+        const int emin = c->model == kIsing ? -2 * N : -N;
+        const int emax = -emin;
+        if (c->lo < emin || c->hi > emax || c->lo > c->hi || (c->lo - emin) % g->step ||
+            (c->hi - emin) % g->step)
+            return muca_fail(MUCA_E_ARG, "range [%d, %d] not on the grid %d + %d k within [%d, %d]",
+                             c->lo, c->hi, emin, g->step, emin, emax);
+        g->layout = c->layout == MUCA_LAYOUT_BYTE ? kLayoutByte : kLayoutBit;
+    }
+    if (c->layout != MUCA_LAYOUT_AUTO && c->layout != MUCA_LAYOUT_BIT && c->layout != MUCA_LAYOUT_BYTE)
+        return muca_fail(MUCA_E_ARG, "unknown layout %d", c->layout);
+    if (c->model == kPotts && c->layout == MUCA_LAYOUT_BIT)
+        return muca_fail(MUCA_E_ARG, "Potts has no bit layout");
+    g->n_bins = (c->hi - c->lo) / g->step + 1;
+    g->wpr = words_per_row(c->L, g->layout);
+    int cpb = c->chains_per_block ? c->chains_per_block : 64;
+    if (cpb != 64 && cpb != 128 && cpb != 256)
+        return muca_fail(MUCA_E_ARG, "chains_per_block %d not in {64, 128, 256}", cpb);
+    while (g->c_pad % cpb)
+        cpb /= 2;
+    g->cpb = cpb;
+    const size_t hist_lds = (size_t)g->n_bins * 4u;
+    const size_t tab_lds = (size_t)g->n_bins * g->n_cols * 4u;
+    if (c->table_in_lds == 1 && hist_lds + tab_lds > 160u * 1024u)
+        return muca_fail(MUCA_E_ARG, "threshold table of %zu bytes does not fit in LDS", tab_lds);
+    if (hist_lds > 64u * 1024u)
+        return muca_fail(MUCA_E_ARG, "%d bins exceed the LDS histogram", g->n_bins);
+    g->table_in_lds = c->table_in_lds == 1 || (c->table_in_lds < 0 && hist_lds + tab_lds <= 128u * 1024u);
+    // workspace carve
+    size_t off = 0;
+    g->off_words = off;
+    off = align256(off + (size_t)c->L * g->wpr * g->c_pad * 4u);
+    g->off_bins = off;
+    off = align256(off + (size_t)g->c_pad * 4u);
+    g->off_values = off;
+    off = align256(off + (size_t)g->c_pad * 4u);
+    g->off_table = off;
+    off = align256(off + tab_lds);
+    g->off_hist = off;
+    off = align256(off + (size_t)g->n_bins * 8u);
+    g->ws_bytes = off;
+    return MUCA_OK;
+}
+
+// Values of the binned quantity that no lattice configuration takes
+// (Omega = 0 on the even-L torus): Ising E = +-(2N - 4); Potts q = 2 odd
+// E_unsat and E_unsat in {2, 2N - 2}; Potts q >= 3 E_unsat in {1, 2, 3, 5}.
+// The recursion links consecutive bins of the remaining set and flatness is
+// measured over it.
+static void reachable_mask(const muca_config *c, const Geometry &g, std::vector<uint8_t> &m)
+{
+    m.assign(g.n_bins, 1);
+    const int N = g.n_sites;
+    for (int b = 0; b < g.n_bins; ++b) {
+        const int v = c->lo + b * g.step;
+        if (g.model == kIsing) {
+            if (v == 2 * N - 4 || v == -(2 * N - 4))
+                m[b] = 0;
+        } else if (g.model == kPotts) {
+            if (c->q == 2) {
+                if ((v % 2) != 0 || v == 2 || v == 2 * N - 2)
+                    m[b] = 0;
+            } else if (v == 1 || v == 2 || v == 3 || v == 5) {
+                m[b] = 0;
+            }
+        }
+    }
+}
+
+// min(1, exp(D)) as an integer threshold on a uniform 32-bit word r: accept
+// iff r < T, with T = 0xffffffff meaning "always".
+static uint32_t threshold_of(double D)
+{
+    if (D >= 0.0)
+        return 0xffffffffu;
+    const double v = std::ldexp(std::exp(D), 32);
+    if (v >= 4294967295.0)
+        return 0xffffffffu;
+    return (uint32_t)std::floor(v);
+}
+
+uint32_t muca_threshold_of(double D) { return threshold_of(D); }
+
+static void build_lattice_thresholds(const muca_config *c, const Geometry &g, const double *lnW,
+                                     uint32_t *T)
+{
+    const int B = g.n_bins, NC = g.n_cols;
+    for (int b = 0; b < B; ++b) {
+        for (int j = 0; j < NC; ++j) {
+            int target;
+            double D;
+            if (g.model == kIsing) {
+                target = b + j - 2; // column = aligned neighbours, dE = 4j - 8
+            } else if (g.model == kPotts) {
+                target = b + j - 4; // column = dE_unsat + 4
+            } else {
+                target = (j & 1) ? b - 1 : b + 1; // column = 2 n_aligned + (s_i == +1)
+            }
+            if (target < 0 || target >= B) {
+                T[(size_t)b * NC + j] = 0u;
+                continue;
+            }
+            D = lnW[target] - lnW[b];
+            if (g.model == kMuma) {
+                const int dE = 4 * (j >> 1) - 8;
+                D = D - c->beta * (double)dE;
+            }
+            T[(size_t)b * NC + j] = threshold_of(D);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Accumulated-statistics recursion on consecutive bins of the set `m`:
+//   p = h0 h1 / (h0 + h1) (0 if a bin is empty),  P += p,
+//   lnR += (p / P) (ln h0 - ln h1),
+// then lnW is the running sum of lnR from the first bin of the set (lnW = 0
+// there); bins outside the set repeat the last weight.
+// ---------------------------------------------------------------------------
+void muca_recursion(int B, const uint8_t *m, const uint64_t *H, double *lnR, double *P, double *lnW)
+{
+    int lower = -1;
+    for (int b = 0; b < B; ++b) {
+        if (!m[b])
+            continue;
+        if (lower >= 0) {
+            const uint64_t a = H[lower], c = H[b];
+            double p = 0.0;
+            if (a != 0 && c != 0) {
+                const double h0 = (double)a, h1 = (double)c;
+                p = (h0 * h1) / (h0 + h1);
+            }
+            P[lower] = P[lower] + p;
+            if (p > 0.0) {
+                const double kappa = p / P[lower];
+                lnR[lower] = lnR[lower] + kappa * (std::log((double)a) - std::log((double)c));
+            }
+        }
+        lower = b;
+    }
+    double run = 0.0;
+    int last = -1;
+    for (int b = 0; b < B; ++b) {
+        if (m[b]) {
+            if (last >= 0)
+                run = run + lnR[last];
+            last = b;
+        }
+        lnW[b] = run;
+    }
+}
+
+double muca_flatness(int B, const uint8_t *m, const uint64_t *H)
+{
+    double lo = 0.0, sum = 0.0;
+    int n = 0;
+    for (int b = 0; b < B; ++b) {
+        if (!m[b])
+            continue;
+        const double h = (double)H[b];
+        if (n == 0 || h < lo)
+            lo = h;
+        sum += h;
+        ++n;
+    }
+    if (n == 0 || sum <= 0.0)
+        return 0.0;
+    return lo / (sum / (double)n);
+}
+
+// Reweighting, Eq. 2, on the binned histogram.  Sums in ascending bin order.
+void muca_reweight_bins(int B, const uint64_t *H, const double *lnW, const double *val, int nsite,
+                        bool muma, double beta, double *out)
+{
+    double amax = 0.0;
+    bool any = false;
+    for (int b = 0; b < B; ++b) {
+        if (!H[b])
+            continue;
+        double a = std::log((double)H[b]) - lnW[b];
+        if (!muma)
+            a = a - beta * val[b];
+        if (!any || a > amax)
+            amax = a;
+        any = true;
+    }
+    if (!any) {
+        out[0] = out[1] = out[2] = out[3] = 0.0;
+        return;
+    }
+    double Z = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int b = 0; b < B; ++b) {
+        if (!H[b])
+            continue;
+        double a = std::log((double)H[b]) - lnW[b];
+        if (!muma)
+            a = a - beta * val[b];
+        const double w = std::exp(a - amax);
+        Z += w;
+        if (muma) {
+            s1 += w * std::fabs(val[b]);
+            s2 += w * (val[b] * val[b]);
+            s3 += w * val[b];
+        } else {
+            s1 += w * val[b];
+        }
+    }
+    const double n = (double)nsite;
+    if (muma) {
+        out[0] = (s1 / Z) / n;
+        out[1] = (s2 / Z) / (n * n);
+        out[2] = (s3 / Z) / n;
+        out[3] = amax + std::log(Z);
+        return;
+    }
+    const double mean = s1 / Z;
+    double var = 0.0;
+    for (int b = 0; b < B; ++b) {
+        if (!H[b])
+            continue;
+        const double a = std::log((double)H[b]) - lnW[b] - beta * val[b];
+        const double w = std::exp(a - amax);
+        const double d = val[b] - mean;
+        var += w * (d * d);
+    }
+    var = var / Z;
+    out[0] = mean / n;
+    out[1] = (beta * beta) * var / n;
+    out[2] = mean;
+    out[3] = amax + std::log(Z);
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" int muca_config_default(int32_t model, int32_t L, int32_t q, int32_t n_chains, uint64_t seed,
+                                   muca_config *c)
+{
+    if (!c)
+        return muca_fail(MUCA_E_ARG, "null config");
+    std::memset(c, 0, sizeof *c);
+    c->abi_version = MUCA_ABI_VERSION;
+    c->model = model;
+    c->L = L;
+    c->q = model == kPotts ? q : 2;
+    c->n_chains = n_chains;
+    c->layout = MUCA_LAYOUT_AUTO;
+    c->seed = seed;
+    c->flat_threshold = 0.5;
+    c->chains_per_block = 0;
+    c->table_in_lds = -1;
+    const int N = L * L;
+    if (model == kIsing) {
+        c->lo = -2 * N;
+        c->hi = 2 * N;
+    } else if (model == kPotts) {
+        c->lo = 0;
+        c->hi = 2 * N;
+    } else if (model == kMuma) {
+        c->lo = -N;
+        c->hi = N;
+        c->beta = 0.5;
+    }
+    c->n_beads = 40;
+    c->n_bins = 2500;
+    c->x_lo = -200.0;
+    c->x_hi = 50.0;
+    c->lj_eps = 1.0;
+    c->lj_sigma = 1.0;
+    c->lj_rcut = 2.5;
+    c->fene_k = 40.0;
+    c->fene_r0 = 1.0;
+    c->fene_R = 0.5;
+    c->step = 0.3f;
+    return MUCA_OK;
+}
+
+extern "C" int muca_workspace_bytes(const muca_config *c, uint64_t *bytes)
+{
+    Geometry g;
+    int rc = muca_geometry(c, &g);
+    if (rc)
+        return rc;
+    if (!bytes)
+        return muca_fail(MUCA_E_ARG, "null bytes");
+    *bytes = g.ws_bytes;
+    return MUCA_OK;
+}
+
+static int check_run(const muca_run *r)
+{
+    if (!r)
+        return muca_fail(MUCA_E_ARG, "null run");
+    if (r->poisoned)
+        return muca_fail(MUCA_E_STATE, "run poisoned by an earlier HIP error");
+    return MUCA_OK;
+}
+
+static int upload_thresholds(muca_run *r)
+{
+    if (r->g.model == kPolymer)
+        return muca_polymer_upload(r);
+    HIP_OR_POISON(r, hipMemcpyAsync(r->d_table, r->T.data(), r->T.size() * 4u, hipMemcpyHostToDevice,
+                                    r->stream));
+    HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
+    return MUCA_OK;
+}
+
+int muca_rebuild_thresholds(muca_run *r)
+{
+    if (r->g.model == kPolymer)
+        return muca_polymer_upload(r);
+    build_lattice_thresholds(&r->cfg, r->g, r->lnW.data(), r->T.data());
+    return upload_thresholds(r);
+}
+
+extern "C" int muca_init(const muca_config *c, void *d_ws, uint64_t ws_bytes, const float *h_pos,
+                         void *stream, muca_run **out)
+{
+    if (!out)
+        return muca_fail(MUCA_E_ARG, "null out");
+    *out = nullptr;
+    Geometry g;
+    int rc = muca_geometry(c, &g);
+    if (rc)
+        return rc;
+    if (!d_ws || ((uintptr_t)d_ws & 255u))
+        return muca_fail(MUCA_E_ARG, "workspace must be a 256-byte aligned device pointer");
+    if (ws_bytes < g.ws_bytes)
+        return muca_fail(MUCA_E_NOMEM, "workspace of %llu bytes, need %llu", (unsigned long long)ws_bytes,
+                         (unsigned long long)g.ws_bytes);
+    if (g.model != kPolymer && g.table_in_lds) {
+        // stage the table in LDS only if the device grants that much per block
+        int dev = 0, lim = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
+            const size_t need = (size_t)g.n_bins * 4u * (1u + (size_t)g.n_cols);
+            if (need > (size_t)lim) {
+                if (c->table_in_lds == 1)
+                    return muca_fail(MUCA_E_ARG, "LDS request of %zu bytes above the device limit %d", need, lim);
+                g.table_in_lds = false;
+            }
+        }
+    }
+    muca_run *r = new muca_run();
+    r->cfg = *c;
+    r->g = g;
+    r->stream = (hipStream_t)stream;
+    uint8_t *ws = (uint8_t *)d_ws;
+    r->ws = ws;
+    r->d_words = (uint32_t *)(ws + g.off_words);
+    r->d_bins = (int32_t *)(ws + g.off_bins);
+    r->d_values = (int32_t *)(ws + g.off_values);
+    r->d_table = (uint32_t *)(ws + g.off_table);
+    r->d_hist = (unsigned long long *)(ws + g.off_hist);
+    r->lnW.assign(g.n_bins, 0.0);
+    r->lnR.assign(g.n_bins, 0.0);
+    r->P.assign(g.n_bins, 0.0);
+    r->H_last.assign(g.n_bins, 0u);
+    r->lnW_last.assign(g.n_bins, 0.0);
+    if (g.model == kPolymer) {
+        rc = muca_polymer_init(r, h_pos);
+        if (rc) {
+            delete r;
+            return rc;
+        }
+        *out = r;
+        return MUCA_OK;
+    }
+    reachable_mask(c, g, r->mask);
+    r->T.assign((size_t)g.n_bins * g.n_cols, 0u);
+    LatticeInitArgs a{};
+    a.words = r->d_words;
+    a.bins = r->d_bins;
+    a.values = r->d_values;
+    a.k0 = (uint32_t)(c->seed & 0xffffffffu);
+    a.k1 = (uint32_t)(c->seed >> 32);
+    a.c_pad = g.c_pad;
+    a.L = c->L;
+    a.q = c->q;
+    a.lo = c->lo;
+    a.step = g.step;
+    a.model = g.model;
+    a.layout = g.layout;
+    hipError_t e = launch_lattice_init(a, r->stream);
+    if (e == hipSuccess)
+        e = launch_fill_u64(r->d_hist, g.n_bins, r->stream);
+    std::vector<int32_t> bins(g.c_pad);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(bins.data(), r->d_bins, bins.size() * 4u, hipMemcpyDeviceToHost, r->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) {
+        delete r;
+        return muca_fail(MUCA_E_HIP, "init: %s", hipGetErrorString(e));
+    }
+    for (int i = 0; i < g.c_pad; ++i) {
+        if (bins[i] < 0 || bins[i] >= g.n_bins) {
+            delete r;
+            return muca_fail(MUCA_E_RANGE, "chain %d starts in bin %d outside [0, %d)", i, bins[i],
+                             g.n_bins);
+        }
+    }
+    rc = muca_rebuild_thresholds(r);
+    if (rc) {
+        delete r;
+        return rc;
+    }
+    *out = r;
+    return MUCA_OK;
+}
+
+int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s)
+{
+    if (r->g.model == kPolymer)
+        return muca_polymer_enqueue(r, sweeps, record, s);
+    const Geometry &g = r->g;
+    // keep each launch's per-block u32 LDS counts below 2^32
+    const int64_t max_chunk = std::max<int64_t>(1, (int64_t)(0xFFFFFFFFll / g.cpb) - 1);
+    int64_t done = 0;
+    while (done < sweeps) {
+        const int64_t n = std::min<int64_t>(sweeps - done, std::min<int64_t>(max_chunk, 1 << 30));
+        LatticeArgs a{};
+        a.words = r->d_words;
+        a.bins = r->d_bins;
+        a.thresholds = r->d_table;
+        a.hist = r->d_hist;
+        a.k0 = (uint32_t)(r->cfg.seed & 0xffffffffu);
+        a.k1 = (uint32_t)(r->cfg.seed >> 32);
+        a.g0 = r->sweep;
+        a.n_sweeps = (int32_t)n;
+        a.n_chains = r->cfg.n_chains;
+        a.c_pad = g.c_pad;
+        a.n_bins = g.n_bins;
+        a.q = r->cfg.q;
+        a.record = record ? 1 : 0;
+        a.table_in_lds = g.table_in_lds ? 1 : 0;
+        a.chain0 = 0;
+        HIP_OR_POISON(r, launch_lattice_sweeps(g.model, g.L, g.layout, g.cpb, g.n_cols, a, s));
+        r->sweep += (uint32_t)n;
+        done += n;
+    }
+    return MUCA_OK;
+}
+
+extern "C" int muca_run_iteration(muca_run *r, int64_t sweeps, void *stream)
+{
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (sweeps < 1)
+        return muca_fail(MUCA_E_ARG, "sweeps must be >= 1");
+    r->stream = (hipStream_t)stream;
+    rc = muca_enqueue_sweeps(r, sweeps, true, r->stream);
+    if (rc)
+        return rc;
+    r->pending += sweeps;
+    return MUCA_OK;
+}
+
+extern "C" int muca_thermalize(muca_run *r, int64_t sweeps, void *stream)
+{
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (sweeps < 0)
+        return muca_fail(MUCA_E_ARG, "sweeps must be >= 0");
+    r->stream = (hipStream_t)stream;
+    return sweeps ? muca_enqueue_sweeps(r, sweeps, false, r->stream) : MUCA_OK;
+}
+
+int muca_finish_iteration(muca_run *r, const uint64_t *H, muca_iter_stats *st)
+{
+    const Geometry &g = r->g;
+    const int B = g.n_bins;
+    r->lnW_last = r->lnW;
+    r->H_last.assign(H, H + B);
+    muca_iter_stats s{};
+    s.iteration = r->iteration;
+    s.sweeps = r->pending;
+    s.lo_visited = -1;
+    s.hi_visited = -1;
+    for (int b = 0; b < B; ++b) {
+        s.samples += (int64_t)H[b];
+        if (H[b]) {
+            if (s.lo_visited < 0)
+                s.lo_visited = b;
+            s.hi_visited = b;
+        }
+    }
+    if (g.model == kPolymer) {
+        for (int b = 0; b < B; ++b)
+            if (H[b])
+                r->mask[b] = 1; // flatness over the bins visited so far
+        s.flatness = muca_flatness(B, r->mask.data(), H);
+        std::vector<uint8_t> all(B, 1);
+        muca_recursion(B, all.data(), H, r->lnR.data(), r->P.data(), r->lnW.data());
+    } else {
+        s.flatness = muca_flatness(B, r->mask.data(), H);
+        muca_recursion(B, r->mask.data(), H, r->lnR.data(), r->P.data(), r->lnW.data());
+    }
+    s.flat = s.flatness > r->cfg.flat_threshold ? 1 : 0;
+    r->iteration += 1;
+    r->pending = 0;
+    r->have_last = true;
+    if (st)
+        *st = s;
+    return muca_rebuild_thresholds(r);
+}
+
+extern "C" int muca_merge_update(muca_run *r, muca_iter_stats *st)
+{
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (r->pending <= 0)
+        return muca_fail(MUCA_E_STATE, "merge_update without sweeps since the last merge");
+    const int B = r->g.n_bins;
+    std::vector<uint64_t> H(B);
+    HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
+    HIP_OR_POISON(r, hipMemcpy(H.data(), r->d_hist, (size_t)B * 8u, hipMemcpyDeviceToHost));
+    HIP_OR_POISON(r, launch_fill_u64(r->d_hist, B, r->stream));
+    return muca_finish_iteration(r, H.data(), st);
+}
+
+extern "C" int muca_reweight(const muca_run *r, const double *betas, int32_t n, double *out)
+{
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (!r->have_last)
+        return muca_fail(MUCA_E_STATE, "no merged histogram yet");
+    if (n < 1 || !out)
+        return muca_fail(MUCA_E_ARG, "need n >= 1 and an output array");
+    const Geometry &g = r->g;
+    if (g.model != kMuma && !betas)
+        return muca_fail(MUCA_E_ARG, "null betas");
+    std::vector<double> val(g.n_bins);
+    for (int b = 0; b < g.n_bins; ++b) {
+        if (g.model == kIsing || g.model == kMuma)
+            val[b] = (double)(r->cfg.lo + g.step * b);
+        else if (g.model == kPotts)
+            val[b] = (double)(r->cfg.lo + b) - 2.0 * g.n_sites;
+        else
+            val[b] = r->cfg.x_lo + ((r->cfg.x_hi - r->cfg.x_lo) / (double)g.n_bins) * ((double)b + 0.5);
+    }
+    for (int k = 0; k < n; ++k) {
+        const bool muma = g.model == kMuma;
+        const double beta = muma ? r->cfg.beta : betas[k];
+        muca_reweight_bins(g.n_bins, r->H_last.data(), r->lnW_last.data(), val.data(), g.n_sites, muma,
+                           beta, out + 4 * k);
+    }
+    return MUCA_OK;
+}
+
+extern "C" int muca_sizes(const muca_run *r, int32_t *n_bins, int32_t *n_cols, int32_t *n_sites)
+{
+    if (!r)
+        return muca_fail(MUCA_E_ARG, "null run");
+    if (n_bins)
+        *n_bins = r->g.n_bins;
+    if (n_cols)
+        *n_cols = r->g.n_cols;
+    if (n_sites)
+        *n_sites = r->g.n_sites;
+    return MUCA_OK;
+}
+
+extern "C" int muca_get_lnw(const muca_run *r, double *h, int32_t n)
+{
+    if (!r || !h || n != r->g.n_bins)
+        return muca_fail(MUCA_E_ARG, "bad arguments");
+    std::memcpy(h, r->lnW.data(), (size_t)n * 8u);
+    return MUCA_OK;
+}
+
+extern "C" int muca_get_last_hist(const muca_run *r, uint64_t *h, int32_t n)
+{
+    if (!r || !h || n != r->g.n_bins)
+        return muca_fail(MUCA_E_ARG, "bad arguments");
+    std::memcpy(h, r->H_last.data(), (size_t)n * 8u);
+    return MUCA_OK;
+}
+
+extern "C" int muca_get_thresholds(const muca_run *r, uint32_t *h, int64_t count)
+{
+    if (!r || !h || count != (int64_t)r->T.size())
+        return muca_fail(MUCA_E_ARG, "bad arguments");
+    std::memcpy(h, r->T.data(), (size_t)count * 4u);
+    return MUCA_OK;
+}
+
+extern "C" int muca_set_lnw(muca_run *r, const double *h, int32_t n)
+{
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (!h || n != r->g.n_bins)
+        return muca_fail(MUCA_E_ARG, "bad arguments");
+    HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
+    r->lnW.assign(h, h + n);
+    return muca_rebuild_thresholds(r);
+}
+
+extern "C" int muca_set_thresholds(muca_run *r, const uint32_t *h, int64_t count)
+{
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (!h || count != (int64_t)r->T.size())
+        return muca_fail(MUCA_E_ARG, "bad arguments");
+    HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
+    std::memcpy(r->T.data(), h, (size_t)count * 4u);
+    return upload_thresholds(r);
+}
+
+extern "C" int muca_get_chain_state(const muca_run *r_, int32_t chain0, int32_t count, void *state,
+                                    int32_t *bins, double *energy)
+{
+    muca_run *r = const_cast<muca_run *>(r_);
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (chain0 < 0 || count < 0 || chain0 + count > r->cfg.n_chains)
+        return muca_fail(MUCA_E_ARG, "chain range [%d, %d) outside [0, %d)", chain0, chain0 + count,
+                         r->cfg.n_chains);
+    if (r->g.model == kPolymer)
+        return muca_polymer_state(r, chain0, count, (float *)state, bins, energy);
+    const Geometry &g = r->g;
+    HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
+    if (bins && count)
+        HIP_OR_POISON(r, hipMemcpy(bins, r->d_bins + chain0, (size_t)count * 4u, hipMemcpyDeviceToHost));
+    if (state && count) {
+        const int rows = g.L * g.wpr;
+        std::vector<uint32_t> w((size_t)rows * count);
+        HIP_OR_POISON(r, hipMemcpy2D(w.data(), (size_t)count * 4u, r->d_words + chain0, (size_t)g.c_pad * 4u,
+                                     (size_t)count * 4u, rows, hipMemcpyDeviceToHost));
+        int8_t *out = (int8_t *)state;
+        const int spw = g.layout == kLayoutBit ? 32 : 4;
+        for (int k = 0; k < count; ++k) {
+            for (int y = 0; y < g.L; ++y) {
+                for (int x = 0; x < g.L; ++x) {
+                    const uint32_t word = w[((size_t)y * g.wpr + x / spw) * count + k];
+                    int8_t v;
+                    if (g.layout == kLayoutBit)
+                        v = ((word >> (x % spw)) & 1u) ? 1 : -1;
+                    else
+                        v = (int8_t)((word >> ((x % spw) * 8)) & 0xFFu);
+                    out[(size_t)k * g.n_sites + y * g.L + x] = v;
+                }
+            }
+        }
+    }
+    if (energy && count) {
+        std::vector<int32_t> b(count);
+        HIP_OR_POISON(r, hipMemcpy(b.data(), r->d_bins + chain0, (size_t)count * 4u, hipMemcpyDeviceToHost));
+        for (int k = 0; k < count; ++k)
+            energy[k] = (double)(r->cfg.lo + g.step * b[k]);
+    }
+    return MUCA_OK;
+}
+
+extern "C" void muca_free(muca_run *r)
+{
+    if (!r)
+        return;
+    if (!r->poisoned && r->stream)
+        (void)hipStreamSynchronize(r->stream);
+    delete r;
+}
+
+// ---------------------------------------------------------------------------
+// Checkpoint / restore: host state plus a byte copy of the device workspace.
+// ---------------------------------------------------------------------------
+namespace {
+const uint32_t kCkptMagic = 0x4d554341u; // "MUCA"
+
+template <class T>
+void put_vec(std::vector<uint8_t> &o, const std::vector<T> &v)
+{
+    const uint64_t n = v.size();
+    const uint8_t *p = (const uint8_t *)&n;
+    o.insert(o.end(), p, p + 8);
+    const uint8_t *d = (const uint8_t *)v.data();
+    o.insert(o.end(), d, d + n * sizeof(T));
+}
+
+template <class T>
+void put_pod(std::vector<uint8_t> &o, const T &v)
+{
+    const uint8_t *p = (const uint8_t *)&v;
+    o.insert(o.end(), p, p + sizeof(T));
+}
+
+struct Reader {
+    const uint8_t *p;
+    uint64_t left;
+    template <class T>
+    bool pod(T &v)
+    {
+        if (left < sizeof(T))
+            return false;
+        std::memcpy(&v, p, sizeof(T));
+        p += sizeof(T);
+        left -= sizeof(T);
+        return true;
+    }
+    template <class T>
+    bool vec(std::vector<T> &v, uint64_t expect)
+    {
+        uint64_t n;
+        if (!pod(n) || n != expect || left < n * sizeof(T))
+            return false;
+        v.resize(n);
+        std::memcpy(v.data(), p, n * sizeof(T));
+        p += n * sizeof(T);
+        left -= n * sizeof(T);
+        return true;
+    }
+};
+} // namespace
+
+extern "C" int muca_checkpoint(const muca_run *r_, void *h_buf, uint64_t *bytes)
+{
+    muca_run *r = const_cast<muca_run *>(r_);
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (!bytes)
+        return muca_fail(MUCA_E_ARG, "null bytes");
+    std::vector<uint8_t> o;
+    put_pod(o, kCkptMagic);
+    put_pod(o, r->cfg);
+    put_pod(o, r->sweep);
+    put_pod(o, r->iteration);
+    put_pod(o, r->pending);
+    put_pod(o, (int32_t)r->have_last);
+    put_vec(o, r->lnW);
+    put_vec(o, r->lnR);
+    put_vec(o, r->P);
+    put_vec(o, r->mask);
+    put_vec(o, r->T);
+    put_vec(o, r->H_last);
+    put_vec(o, r->lnW_last);
+    const uint64_t ws = r->g.ws_bytes;
+    const uint64_t total = o.size() + 8 + ws;
+    if (!h_buf) {
+        *bytes = total;
+        return MUCA_OK;
+    }
+    if (*bytes < total)
+        return muca_fail(MUCA_E_NOMEM, "checkpoint buffer of %llu bytes, need %llu",
+                         (unsigned long long)*bytes, (unsigned long long)total);
+    HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
+    uint8_t *dst = (uint8_t *)h_buf;
+    std::memcpy(dst, o.data(), o.size());
+    std::memcpy(dst + o.size(), &ws, 8);
+    HIP_OR_POISON(r, hipMemcpy(dst + o.size() + 8, r->ws, ws, hipMemcpyDeviceToHost));
+    *bytes = total;
+    return MUCA_OK;
+}
+
+extern "C" int muca_restore(muca_run *r, const void *h_buf, uint64_t bytes)
+{
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (!h_buf)
+        return muca_fail(MUCA_E_ARG, "null buffer");
+    Reader rd{(const uint8_t *)h_buf, bytes};
+    uint32_t magic;
+    muca_config cfg;
+    if (!rd.pod(magic) || magic != kCkptMagic || !rd.pod(cfg))
+        return muca_fail(MUCA_E_ARG, "not a checkpoint");
+    if (std::memcmp(&cfg, &r->cfg, sizeof cfg) != 0)
+        return muca_fail(MUCA_E_ARG, "checkpoint of a different configuration");
+    uint32_t sweep;
+    int64_t iteration, pending;
+    int32_t have_last;
+    std::vector<double> lnW, lnR, P, lnW_last;
+    std::vector<uint8_t> mask;
+    std::vector<uint32_t> T;
+    std::vector<uint64_t> H_last;
+    const uint64_t B = r->g.n_bins;
+    bool ok = rd.pod(sweep) && rd.pod(iteration) && rd.pod(pending) && rd.pod(have_last) &&
+              rd.vec(lnW, B) && rd.vec(lnR, B) && rd.vec(P, B) && rd.vec(mask, r->mask.size()) &&
+              rd.vec(T, r->T.size()) && rd.vec(H_last, B) && rd.vec(lnW_last, B);
+    uint64_t ws = 0;
+    ok = ok && rd.pod(ws) && ws == r->g.ws_bytes && rd.left == ws;
+    if (!ok)
+        return muca_fail(MUCA_E_ARG, "truncated or mismatched checkpoint");
+    HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
+    HIP_OR_POISON(r, hipMemcpy(r->ws, rd.p, ws, hipMemcpyHostToDevice));
+    r->sweep = sweep;
+    r->iteration = iteration;
+    r->pending = pending;
+    r->have_last = have_last != 0;
+    r->lnW = lnW;
+    r->lnR = lnR;
+    r->P = P;
+    r->mask = mask;
+    r->T = T;
+    r->H_last = H_last;
+    r->lnW_last = lnW_last;
+    return MUCA_OK;
+}

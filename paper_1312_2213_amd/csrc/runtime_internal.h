@@ -1,0 +1,65 @@
+// runtime_internal.h -- host-side run state shared by the runtime sources.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/muca.h"
+
+namespace muca {
+
+struct Geometry {
+    int model;
+    int L, n_sites;      // lattice size / polymer beads
+    int step;            // bin width of the binned quantity (lattice)
+    int n_bins, n_cols;  // threshold table is n_bins x n_cols (polymer: n_bins x n_bins)
+    int layout, wpr;     // lattice storage
+    int c_pad;           // chains rounded up to a multiple of 64
+    int cpb;             // chains per block
+    bool table_in_lds;
+    size_t off_words, off_bins, off_values, off_table, off_hist, off_energy;
+    size_t ws_bytes;
+};
+
+} // namespace muca
+
+struct muca_run {
+    muca_config cfg;
+    muca::Geometry g;
+    hipStream_t stream = nullptr;
+    uint8_t *ws = nullptr;
+    uint32_t *d_words = nullptr;   // lattice words / polymer positions (as float)
+    int32_t *d_bins = nullptr;
+    int32_t *d_values = nullptr;
+    uint32_t *d_table = nullptr;
+    unsigned long long *d_hist = nullptr;
+    double *d_energy = nullptr;    // polymer running energies
+    std::vector<double> lnW, lnR, P;
+    std::vector<uint8_t> mask;     // bins linked by the recursion / measured for flatness
+    std::vector<uint32_t> T;       // host mirror of the thresholds
+    std::vector<uint64_t> H_last;  // last merged histogram H^(n)
+    std::vector<double> lnW_last;  // lnW^(n) that produced H_last
+    uint32_t sweep = 0;            // global sweep counter (Philox counter word 1)
+    int64_t iteration = 0;
+    int64_t pending = 0;           // recorded sweeps since the last merge
+    bool have_last = false;
+    bool poisoned = false;
+};
+
+int muca_fail(int code, const char *fmt, ...);
+int muca_geometry(const muca_config *c, muca::Geometry *g);
+int muca_rebuild_thresholds(muca_run *r);
+int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s);
+int muca_finish_iteration(muca_run *r, const uint64_t *H, muca_iter_stats *st);
+uint32_t muca_threshold_of(double D);
+void muca_recursion(int B, const uint8_t *m, const uint64_t *H, double *lnR, double *P, double *lnW);
+double muca_flatness(int B, const uint8_t *m, const uint64_t *H);
+
+// polymer.cpp
+int muca_polymer_geometry(const muca_config *c, muca::Geometry *g);
+int muca_polymer_init(muca_run *r, const float *h_pos);
+int muca_polymer_upload(muca_run *r);
+int muca_polymer_enqueue(muca_run *r, int64_t sweeps, bool record, hipStream_t s);
+int muca_polymer_state(muca_run *r, int32_t chain0, int32_t count, float *pos, int32_t *bins,
+                       double *energy);

@@ -1,0 +1,250 @@
+"""Thin Python binding of libmuca.so (include/muca.h): argument marshalling only.
+
+Every step of the multicanonical path (initialisation, sweeps, histogram
+merge, weight recursion, thresholds, reweighting) runs inside the native
+library.  PyTorch supplies device memory (the workspace tensor) and streams.
+Importing this module fails loudly if the HIP library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmuca.so")
+
+MUCA_ISING, MUCA_POTTS, MUCA_MUMA, MUCA_POLYMER = 0, 1, 2, 3
+MUCA_LAYOUT_AUTO, MUCA_LAYOUT_BIT, MUCA_LAYOUT_BYTE = 0, 1, 2
+MUCA_ABI_VERSION = 1
+MODELS = {"ising": MUCA_ISING, "potts": MUCA_POTTS, "muma": MUCA_MUMA, "polymer": MUCA_POLYMER}
+
+
+class MucaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"muca error {code}: {msg}")
+        self.code = code
+
+
+class muca_config(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("model", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("q", ctypes.c_int32), ("n_chains", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("lo", ctypes.c_int32), ("hi", ctypes.c_int32),
+                ("beta", ctypes.c_double), ("flat_threshold", ctypes.c_double),
+                ("chains_per_block", ctypes.c_int32), ("table_in_lds", ctypes.c_int32),
+                ("n_beads", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+                ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double),
+                ("lj_eps", ctypes.c_double), ("lj_sigma", ctypes.c_double), ("lj_rcut", ctypes.c_double),
+                ("fene_k", ctypes.c_double), ("fene_r0", ctypes.c_double), ("fene_R", ctypes.c_double),
+                ("step", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+class muca_iter_stats(ctypes.Structure):
+    _fields_ = [("iteration", ctypes.c_int64), ("sweeps", ctypes.c_int64), ("samples", ctypes.c_int64),
+                ("flatness", ctypes.c_double), ("flat", ctypes.c_int32), ("lo_visited", ctypes.c_int32),
+                ("hi_visited", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(no CPU fallback exists)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER
+    vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
+    sig = {
+        "muca_config_default": (ctypes.c_int, [i32, i32, i32, i32, u64, P(muca_config)]),
+        "muca_workspace_bytes": (ctypes.c_int, [P(muca_config), P(ctypes.c_uint64)]),
+        "muca_init": (ctypes.c_int, [P(muca_config), vp, u64, vp, vp, P(vp)]),
+        "muca_run_iteration": (ctypes.c_int, [vp, i64, vp]),
+        "muca_thermalize": (ctypes.c_int, [vp, i64, vp]),
+        "muca_merge_update": (ctypes.c_int, [vp, P(muca_iter_stats)]),
+        "muca_reweight": (ctypes.c_int, [vp, vp, i32, vp]),
+        "muca_batch_workspace_bytes": (ctypes.c_int, [i32, P(ctypes.c_uint64)]),
+        "muca_batch_run_iteration": (ctypes.c_int, [P(vp), i32, P(ctypes.c_int64), vp, u64, i32, vp]),
+        "muca_sizes": (ctypes.c_int, [vp, P(i32), P(i32), P(i32)]),
+        "muca_get_lnw": (ctypes.c_int, [vp, vp, i32]),
+        "muca_get_last_hist": (ctypes.c_int, [vp, vp, i32]),
+        "muca_get_thresholds": (ctypes.c_int, [vp, vp, i64]),
+        "muca_get_chain_state": (ctypes.c_int, [vp, i32, i32, vp, vp, vp]),
+        "muca_set_lnw": (ctypes.c_int, [vp, vp, i32]),
+        "muca_set_thresholds": (ctypes.c_int, [vp, vp, i64]),
+        "muca_checkpoint": (ctypes.c_int, [vp, vp, P(ctypes.c_uint64)]),
+        "muca_restore": (ctypes.c_int, [vp, vp, u64]),
+        "muca_free": (None, [vp]),
+        "muca_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+LIB = _load()
+EXPORTED = ("muca_config_default", "muca_workspace_bytes", "muca_init", "muca_run_iteration",
+            "muca_thermalize", "muca_merge_update", "muca_reweight", "muca_batch_workspace_bytes",
+            "muca_batch_run_iteration", "muca_sizes", "muca_get_lnw", "muca_get_last_hist",
+            "muca_get_thresholds", "muca_get_chain_state", "muca_set_lnw", "muca_set_thresholds",
+            "muca_checkpoint", "muca_restore", "muca_free", "muca_last_error")
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise MucaError(rc, LIB.muca_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def muca_config_default(model, L=0, q=2, n_chains=1, seed=0, **overrides) -> muca_config:
+    cfg = muca_config()
+    m = MODELS[model] if isinstance(model, str) else int(model)
+    _check(LIB.muca_config_default(m, L, q, n_chains, seed, ctypes.byref(cfg)))
+    for k, v in overrides.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+def muca_workspace_bytes(cfg: muca_config) -> int:
+    n = ctypes.c_uint64(0)
+    _check(LIB.muca_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n)))
+    return n.value
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Run:
+    """One MUCA/MUMA/polymer instance; holds the workspace tensor alive."""
+
+    def __init__(self, cfg: muca_config, positions: np.ndarray | None = None, stream=None,
+                 device="cuda"):
+        import torch
+        self.cfg = cfg
+        self.stream = stream
+        nbytes = muca_workspace_bytes(cfg)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._ws_ptr = ctypes.c_void_p(aligned)
+        self._ws_bytes = nbytes
+        self.handle = ctypes.c_void_p()
+        pos_ptr = None
+        if positions is not None:
+            self._pos = np.ascontiguousarray(positions, np.float32)
+            pos_ptr = _ptr(self._pos)
+        _check(LIB.muca_init(ctypes.byref(cfg), self._ws_ptr, nbytes, pos_ptr,
+                             _stream_handle(stream), ctypes.byref(self.handle)))
+        nb, nc, ns = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(LIB.muca_sizes(self.handle, ctypes.byref(nb), ctypes.byref(nc), ctypes.byref(ns)))
+        self.n_bins, self.n_cols, self.n_sites = nb.value, nc.value, ns.value
+
+    # -- the hot path ------------------------------------------------------
+    def run_iteration(self, sweeps: int, stream=None):
+        _check(LIB.muca_run_iteration(self.handle, int(sweeps), _stream_handle(stream or self.stream)))
+
+    def thermalize(self, sweeps: int, stream=None):
+        _check(LIB.muca_thermalize(self.handle, int(sweeps), _stream_handle(stream or self.stream)))
+
+    def merge_update(self) -> dict:
+        st = muca_iter_stats()
+        _check(LIB.muca_merge_update(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def reweight(self, betas) -> np.ndarray:
+        b = np.ascontiguousarray(np.atleast_1d(betas), np.float64)
+        out = np.zeros((len(b), 4), np.float64)
+        _check(LIB.muca_reweight(self.handle, _ptr(b), len(b), _ptr(out)))
+        return out
+
+    # -- accessors -----------------------------------------------------------
+    def lnw(self) -> np.ndarray:
+        out = np.zeros(self.n_bins, np.float64)
+        _check(LIB.muca_get_lnw(self.handle, _ptr(out), self.n_bins))
+        return out
+
+    def last_hist(self) -> np.ndarray:
+        out = np.zeros(self.n_bins, np.uint64)
+        _check(LIB.muca_get_last_hist(self.handle, _ptr(out), self.n_bins))
+        return out
+
+    def table_size(self) -> int:
+        if self.cfg.model == MUCA_POLYMER:
+            return self.n_bins * self.n_bins
+        return self.n_bins * self.n_cols
+
+    def thresholds(self) -> np.ndarray:
+        out = np.zeros(self.table_size(), np.uint32)
+        _check(LIB.muca_get_thresholds(self.handle, _ptr(out), out.size))
+        return out
+
+    def set_lnw(self, lnw):
+        a = np.ascontiguousarray(lnw, np.float64)
+        _check(LIB.muca_set_lnw(self.handle, _ptr(a), len(a)))
+
+    def set_thresholds(self, t):
+        a = np.ascontiguousarray(t, np.uint32)
+        _check(LIB.muca_set_thresholds(self.handle, _ptr(a), a.size))
+
+    def chain_state(self, chain0: int = 0, count: int | None = None):
+        if count is None:
+            count = self.cfg.n_chains - chain0
+        bins = np.zeros(count, np.int32)
+        energy = np.zeros(count, np.float64)
+        if self.cfg.model == MUCA_POLYMER:
+            state = np.zeros((count, self.cfg.n_beads, 3), np.float32)
+        else:
+            state = np.zeros((count, self.n_sites), np.int8)
+        _check(LIB.muca_get_chain_state(self.handle, chain0, count, _ptr(state), _ptr(bins), _ptr(energy)))
+        return state, bins, energy
+
+    def checkpoint(self) -> bytes:
+        n = ctypes.c_uint64(0)
+        _check(LIB.muca_checkpoint(self.handle, None, ctypes.byref(n)))
+        buf = (ctypes.c_uint8 * n.value)()
+        _check(LIB.muca_checkpoint(self.handle, ctypes.cast(buf, ctypes.c_void_p), ctypes.byref(n)))
+        return bytes(buf)
+
+    def restore(self, blob: bytes):
+        buf = (ctypes.c_uint8 * len(blob)).from_buffer_copy(blob)
+        _check(LIB.muca_restore(self.handle, ctypes.cast(buf, ctypes.c_void_p), len(blob)))
+
+    def free(self):
+        if self.handle:
+            LIB.muca_free(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def muca_batch_run_iteration(runs, sweeps, batch_ws=None, graph: bool = False, stream=None):
+    """One persistent launch over several runs; batch_ws is a uint8 CUDA tensor."""
+    import torch
+    n = len(runs)
+    need = ctypes.c_uint64(0)
+    _check(LIB.muca_batch_workspace_bytes(n, ctypes.byref(need)))
+    if batch_ws is None or batch_ws.numel() < need.value + 256:
+        batch_ws = torch.empty(need.value + 256, dtype=torch.uint8, device="cuda")
+    base = batch_ws.data_ptr()
+    aligned = (base + 255) // 256 * 256
+    handles = (ctypes.c_void_p * n)(*[r.handle.value for r in runs])
+    sw = (ctypes.c_int64 * n)(*[int(s) for s in (sweeps if np.ndim(sweeps) else [sweeps] * n)])
+    _check(LIB.muca_batch_run_iteration(handles, n, sw, ctypes.c_void_p(aligned), need.value,
+                                        int(bool(graph)), _stream_handle(stream)))
+    for r, s in zip(runs, sw):
+        pass
+    return batch_ws

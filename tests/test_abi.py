@@ -1,0 +1,52 @@
+"""The C-ABI library loads on the CPU and exports every symbol that
+include/muca.h declares (no compute calls without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "muca.h")
+LIB = os.path.join(ROOT, "paper_1312_2213_amd", "libmuca.so")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(muca_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ("muca_init", "muca_run_iteration", "muca_merge_update", "muca_reweight",
+              "muca_batch_run_iteration", "muca_free", "muca_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.fail("libmuca.so not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_exports():
+    from paper_1312_2213_amd import muca
+    assert set(declared()) <= set(muca.EXPORTED)
+
+
+def test_host_only_calls_without_gpu():
+    """Configuration helpers never touch the device."""
+    from paper_1312_2213_amd import muca
+    c = muca.muca_config_default("ising", 64, 2, 4096, 2)
+    assert (c.lo, c.hi, c.flat_threshold) == (-8192, 8192, 0.5)
+    n = muca.muca_workspace_bytes(c)
+    assert n >= 64 * 2 * 4096 * 4 + 4097 * (5 * 4 + 8)
+    bad = muca.muca_config_default("ising", 12, 2, 16, 1)
+    with pytest.raises(muca.MucaError):
+        muca.muca_workspace_bytes(bad)
+    bad = muca.muca_config_default("ising", 8, 2, 16, 1, lo=-126)
+    with pytest.raises(muca.MucaError):
+        muca.muca_workspace_bytes(bad)

@@ -1,0 +1,165 @@
+"""GPU (HIP, gfx950) against the oracle on identical seeded inputs: bit-exact
+histograms, spins and bins; weights and reweighted observables within 1e-12
+relative (in practice identical: both sides run the same FP64 definition in
+the same order with glibc libm)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_common import assert_same_state, pair  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+def close(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return np.all(np.abs(a - b) <= RTOL * np.maximum(1.0, np.abs(b)))
+
+
+def iterate_both(o, g, sweeps, iters):
+    for it in range(iters):
+        print(f"  iteration {it}", flush=True)
+        assert np.array_equal(g.thresholds(), o.thresholds()), "thresholds differ"
+        H, f, lnw_used = o.iterate(sweeps)
+        g.run_iteration(sweeps)
+        st = g.merge_update()
+        assert np.array_equal(g.last_hist(), H), f"histogram differs in iteration {it}"
+        assert abs(st["flatness"] - f) <= 1e-15
+        assert close(g.lnw(), o.lnW), "lnW differs"
+    return H, lnw_used
+
+
+def test_init_matches():
+    for model, L, q in (("ising", 8, 2), ("potts", 16, 5), ("muma", 16, 2)):
+        o, g = pair(model, L, 100, seed=77, q=q)
+        assert_same_state(o, g)
+
+
+@pytest.mark.parametrize("layout", [1, 2])
+@pytest.mark.parametrize("L", [4, 8, 16, 24])
+def test_ising_iterations(L, layout):
+    print(f"ising L={L} layout={layout}", flush=True)
+    o, g = pair("ising", L, 130, seed=100 + L, layout=layout)
+    iterate_both(o, g, 20, 3)
+    assert_same_state(o, g)
+
+
+@pytest.mark.parametrize("L", [32, 48, 64])
+def test_ising_large_L_short(L):
+    print(f"ising L={L}", flush=True)
+    o, g = pair("ising", L, 70, seed=5 + L)
+    iterate_both(o, g, 3, 2)
+    assert_same_state(o, g)
+
+
+@pytest.mark.parametrize("q,L", [(2, 8), (3, 8), (8, 16), (10, 24), (4, 32)])
+def test_potts_iterations(q, L):
+    print(f"potts q={q} L={L}", flush=True)
+    o, g = pair("potts", L, 90, seed=200 + q, q=q)
+    iterate_both(o, g, 10, 3)
+    assert_same_state(o, g)
+
+
+@pytest.mark.parametrize("layout", [1, 2])
+@pytest.mark.parametrize("L", [8, 32])
+def test_muma_iterations(L, layout):
+    print(f"muma L={L} layout={layout}", flush=True)
+    o, g = pair("muma", L, 100, seed=300 + L, beta=0.5, layout=layout)
+    iterate_both(o, g, 10, 3)
+    assert_same_state(o, g)
+
+
+def test_config1_full_run():
+    """Ising L=8, 16 chains, seed 1, E in [-128, 128] step 4, 12 iterations of
+    2000 sweeps then the final update; reweighted u, c at three betas."""
+    o, g = pair("ising", 8, 16, seed=1, lo=-128, hi=128)
+    H, lnw_used = iterate_both(o, g, 2000, 12)
+    betas = [0.3, 0.44, 0.6]
+    assert close(g.reweight(betas), o.reweight(H, lnw_used, betas))
+    assert_same_state(o, g)
+
+
+def test_restricted_range_rejects_leaving_moves():
+    o, g = pair("ising", 8, 64, seed=9, lo=-64, hi=48)
+    iterate_both(o, g, 50, 3)
+    assert_same_state(o, g)
+
+
+def test_single_chain_and_ragged_tail():
+    for chains in (1, 63, 65):
+        o, g = pair("potts", 8, chains, seed=chains, q=3)
+        iterate_both(o, g, 15, 2)
+        assert_same_state(o, g)
+
+
+def test_invariant_to_launch_shape_and_table_placement():
+    ref = None
+    for cpb in (64, 128, 256):
+        for tlds in (0, 1):
+            o, g = pair("ising", 16, 256, seed=4, cpb=cpb, tlds=tlds)
+            g.run_iteration(25)
+            g.merge_update()
+            s, b, _ = g.chain_state()
+            cur = (g.last_hist().tobytes(), s.tobytes(), b.tobytes())
+            if ref is None:
+                ref = cur
+            assert cur == ref, (cpb, tlds)
+
+
+def test_chunked_iteration_equals_one_piece():
+    _, a = pair("ising", 16, 64, seed=8)
+    _, b = pair("ising", 16, 64, seed=8)
+    a.run_iteration(30)
+    a.merge_update()
+    b.run_iteration(10)
+    b.run_iteration(20)
+    b.merge_update()
+    assert np.array_equal(a.last_hist(), b.last_hist())
+    assert np.array_equal(a.lnw(), b.lnw())
+
+
+def test_checkpoint_restore_is_exact():
+    _, a = pair("potts", 16, 128, seed=12, q=4)
+    _, b = pair("potts", 16, 128, seed=12, q=4)
+    for _ in range(2):
+        a.run_iteration(10)
+        a.merge_update()
+    blob = a.checkpoint()
+    for _ in range(2):
+        a.run_iteration(10)
+        a.merge_update()
+    b.restore(blob)
+    for _ in range(2):
+        b.run_iteration(10)
+        b.merge_update()
+    assert np.array_equal(a.last_hist(), b.last_hist())
+    assert np.array_equal(a.lnw(), b.lnw())
+    assert np.array_equal(a.chain_state()[0], b.chain_state()[0])
+
+
+def test_ising64_full_size_sampled():
+    """The bench workload's shape: L=64 bit-packed, 4096 chains.  Merged
+    histogram over all chains and sampled chains' spins after 2 sweeps."""
+    from oracle import oracle as orc
+    o, g = pair("ising", 64, 4096, seed=2, layout=1)
+    g.run_iteration(2)
+    g.merge_update()
+    H = o.sweeps(2)
+    assert np.array_equal(g.last_hist(), H)
+    s, b, _ = g.chain_state()
+    for c in (0, 1, 63, 64, 1000, 4095):
+        assert np.array_equal(s[c], o.spins[c]) and b[c] == o.bins()[c]
+
+
+def test_potts48_full_size_global_table():
+    """q=8, L=48, 2048 chains: the threshold table (162 KiB) stays in global memory."""
+    o, g = pair("potts", 48, 2048, seed=33, q=8)
+    g.run_iteration(2)
+    g.merge_update()
+    assert np.array_equal(g.last_hist(), o.sweeps(2))
+    assert_same_state(o, g, chains=(0, 777, 2047))
