@@ -71,7 +71,8 @@ typedef struct muca_config {
                                step 1, MUMA M step 2)                          */
     double beta;            /* MUMA: fixed inverse temperature                 */
     double flat_threshold;  /* flat iff min(H)/mean(H) over the flatness set > this */
-    int32_t chains_per_block; /* 0 = auto, else 64, 128 or 256               */
+    int32_t chains_per_block; /* 0 = auto; chains_per_block x lanes_per_chain
+                                 must be 64, 128 or 256 threads              */
     int32_t table_in_lds;   /* -1 auto, 0 thresholds read from global memory, 1 staged in LDS */
     /* polymer */
     int32_t n_beads;        /* 2..64                                           */
@@ -80,7 +81,8 @@ typedef struct muca_config {
     double lj_eps, lj_sigma, lj_rcut;
     double fene_k, fene_r0, fene_R; /* FENE -(K/2) R^2 ln(1-((r-r0)/R)^2)     */
     float step;             /* side of the displacement cube                   */
-    int32_t reserved;
+    int32_t lanes_per_chain; /* lattice: 0 = auto, else 1, 2, 4 or 16 lanes share
+                                one chain's random-number work                 */
 } muca_config;
 
 typedef struct muca_iter_stats {

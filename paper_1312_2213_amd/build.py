@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmuca.so")
 
-SOURCES = ["lattice.hip", "runtime.cpp", "polymer_host.cpp", "batch.cpp"]
+SOURCES = ["lattice_ising.hip", "lattice_muma.hip", "lattice_potts.hip", "lattice_common.hip",
+           "runtime.cpp", "polymer_host.cpp", "batch.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
           "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]

@@ -1,0 +1,426 @@
+// lattice_impl.h -- Metropolis sweeps of many independent 2D lattice chains that
+// share one multicanonical weight table (gfx950).
+//
+// Method (arXiv:1312.2213): every realisation runs single-site updates with
+// the weight W(E) of Eq. 1 (Ising H = -sum s_i s_j, Potts
+// H = -sum delta(s_i, s_j)) or, for the multimagnetic ensemble of Eq. 3, the
+// weight exp(-beta E) W(M); after each sweep the chain's bin is added to the
+// histogram that is merged over all chains (parallel-scheme paragraph).
+//
+// Mapping to the hardware:
+//  * one chain per lane; a wavefront runs 64 chains in lockstep on the same
+//    site, so the lattice words of 64 chains are 64 consecutive dwords;
+//  * a sweep streams the lattice row by row through registers: rows y-1, y,
+//    y+1 are held in VGPRs and row y+3 is prefetched while y is processed;
+//    every site update works on registers with compile-time bit positions;
+//  * Metropolis acceptance is one integer compare against a threshold
+//    T[bin][column] (staged in LDS when it fits), so no exp() is evaluated;
+//  * the per-block histogram lives in LDS (u32) and is added to the global
+//    u64 histogram with atomics once per launch.
+#pragma once
+#include <utility>
+
+#include "muca_internal.h"
+#include "philox.h"
+
+namespace muca {
+
+template <int L, int LAYOUT>
+struct Geom {
+    static constexpr int kBits = LAYOUT == kLayoutBit ? 1 : 8;
+    static constexpr int kSpw = 32 / kBits;
+    static constexpr int kWpr = (L + kSpw - 1) / kSpw;
+};
+
+template <int MODEL>
+struct Cols {
+    static constexpr int value = MODEL == kIsing ? 5 : (MODEL == kPotts ? 9 : 10);
+};
+
+// Spin code of site x of a row: BIT layout -> the bit (1 = +1); BYTE layout
+// (int8 +-1) -> the sign bit (1 = -1).  Equal codes <=> equal spins.
+template <int L, int LAYOUT, int W>
+__device__ __forceinline__ uint32_t spin_code(const uint32_t (&R)[W], int x)
+{
+    using G = Geom<L, LAYOUT>;
+    if (LAYOUT == kLayoutBit)
+        return (R[x / G::kSpw] >> (x % G::kSpw)) & 1u;
+    return (R[x / G::kSpw] >> ((x % G::kSpw) * 8 + 7)) & 1u;
+}
+
+template <int L, int W>
+__device__ __forceinline__ uint32_t colour(const uint32_t (&R)[W], int x)
+{
+    return (R[x / 4] >> ((x % 4) * 8)) & 0xFFu;
+}
+
+// ---------------------------------------------------------------------------
+// Random words of one row.  With LPC lanes per chain, lane j of a chain's
+// group computes the Philox calls j, j + LPC, ... of the row and every site
+// reads its word from the owning lane by a DPP broadcast (quad_perm within
+// quads, row_newbcast within rows of 16).  The counters, and so the words,
+// are those of the one-lane-per-chain order.
+// ---------------------------------------------------------------------------
+template <int L, int LPC, int WPS>
+struct RowRng {
+    static constexpr int kSpc = 4 / WPS;                       // sites per Philox call
+    static constexpr int kCalls = L / kSpc;                    // calls per row
+    static constexpr int kPerLane = (kCalls + LPC - 1) / LPC;  // calls per lane
+    uint32_t w[kPerLane * 4];
+
+    __device__ __forceinline__ void fill(uint32_t chain, uint32_t g, int y, uint32_t j, uint32_t k0, uint32_t k1)
+    {
+#pragma unroll
+        for (int m = 0; m < kPerLane; ++m) {
+            uint32_t call = j + (uint32_t)(LPC * m);
+            if (kCalls % LPC)
+                call = call < (uint32_t)kCalls ? call : (uint32_t)kCalls - 1u; // surplus lanes: any valid call
+            const Words4 r = philox4x32_10(chain, g, (uint32_t)(y * kCalls) + call, kTagSweep, k0, k1);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                w[4 * m + t] = r.w[t];
+        }
+    }
+
+    // word WI (0..WPS-1) of site X of the row
+    template <int X, int WI>
+    __device__ __forceinline__ uint32_t get() const
+    {
+        constexpr int call = X / kSpc;
+        constexpr int src = call % LPC;
+        constexpr int reg = (call / LPC) * 4 + (X % kSpc) * WPS + WI;
+        if constexpr (LPC == 1) {
+            return w[reg];
+        } else if constexpr (LPC == 2) {
+            constexpr int pat = src | (src << 2) | ((2 + src) << 4) | ((2 + src) << 6);
+            return (uint32_t)__builtin_amdgcn_mov_dpp((int)w[reg], pat, 0xF, 0xF, false);
+        } else if constexpr (LPC == 4) {
+            return (uint32_t)__builtin_amdgcn_mov_dpp((int)w[reg], src * 0x55, 0xF, 0xF, false);
+        } else {
+            static_assert(LPC == 16, "lanes per chain: 1, 2, 4 or 16");
+            return (uint32_t)__builtin_amdgcn_mov_dpp((int)w[reg], 0x150 + src, 0xF, 0xF, false);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Ising / MUMA.  Rows are held bit-packed in registers whatever the storage
+// layout (bit 1 = spin +1, W1 = ceil(L/32) words, unused high bits zero).
+// Before the sites of a word are visited, the misalignment of every site
+// with its right, up and down neighbours is counted bit-parallel into two bit
+// planes (s0 = parity, s1 = majority), and with its left neighbour into ML.
+// None of these neighbours changes before the site's own attempt, except the
+// left one (the previous site), whose flip f is folded in per site; and, for
+// a row of one word, the right neighbour of the last site (site 0 of the
+// same row), which is read from the current word.
+// ---------------------------------------------------------------------------
+template <int L>
+struct Row1 {
+    static constexpr int W = (L + 31) / 32;
+};
+
+template <int MODEL, int L, int LPC, int WI, int K>
+__device__ __forceinline__ void ising_bit(uint32_t &F, uint32_t &f, int32_t &bidx, const RowRng<L, LPC, 1> &rng,
+                                          uint32_t S, uint32_t s0, uint32_t s1, uint32_t ML, uint32_t MU,
+                                          uint32_t MD, const uint32_t *__restrict__ T)
+{
+    constexpr int X = 32 * WI + K; // column of the site
+    constexpr int NC = Cols<MODEL>::value;
+    const uint32_t r = min(rng.template get<X, 0>(), 0xFFFFFFFEu); // accept iff r < T (T = ~0: always)
+    uint32_t ml = (ML >> K) & 1u;
+    if constexpr (K > 0)
+        ml ^= f; // the previous site of this word may have flipped
+    int32_t nmis;
+    if constexpr (Row1<L>::W == 1 && X == L - 1 && L > 1) {
+        // right neighbour is site 0 of this word: read its current value
+        const uint32_t s = (S >> K) & 1u;
+        const uint32_t mr = s ^ ((S ^ F) & 1u);
+        nmis = (int32_t)(mr + ((MU >> K) & 1u) + ((MD >> K) & 1u) + ml);
+    } else {
+        nmis = (int32_t)((((s1 >> K) & 1u) << 1) + ((s0 >> K) & 1u) + ml);
+    }
+    int32_t col, dstep;
+    if constexpr (MODEL == kIsing) {
+        col = 4 - nmis;          // aligned neighbours
+        dstep = (2 - nmis) * NC; // dE = 4 (n_al - 2): one bin per 4
+    } else {
+        const int32_t plus = (int32_t)((S >> K) & 1u);
+        col = 2 * (4 - nmis) + plus;
+        dstep = plus ? -NC : NC; // M changes by -2 s_i: one bin per 2
+    }
+    const uint32_t t = T[bidx + col];
+    f = r < t ? 1u : 0u;
+    F |= f << K;
+    bidx += (int32_t)f * dstep;
+}
+
+template <int MODEL, int L, int LPC, int WI, int... K>
+__device__ __forceinline__ void ising_word(const uint32_t (&up)[Row1<L>::W], uint32_t (&cur)[Row1<L>::W],
+                                           const uint32_t (&dn)[Row1<L>::W], int32_t &bidx,
+                                           const RowRng<L, LPC, 1> &rng, const uint32_t *__restrict__ T,
+                                           std::integer_sequence<int, K...>)
+{
+    constexpr int W = Row1<L>::W;
+    constexpr int NB = (L - 32 * WI) < 32 ? (L - 32 * WI) : 32; // sites in this word
+    const uint32_t S = cur[WI];
+    const uint32_t nextbit = (WI + 1 < W) ? (cur[WI + 1] & 1u) : (cur[0] & 1u);
+    const uint32_t prevbit = (WI > 0) ? (cur[WI > 0 ? WI - 1 : 0] >> 31) : ((cur[W - 1] >> ((L - 1) % 32)) & 1u);
+    const uint32_t Rn = (S >> 1) | (nextbit << (NB - 1));
+    const uint32_t Ln = (S << 1) | prevbit;
+    const uint32_t MR = S ^ Rn, MU = S ^ up[WI], MD = S ^ dn[WI], ML = S ^ Ln;
+    const uint32_t s0 = MR ^ MU ^ MD;
+    const uint32_t s1 = (MR & MU) | (MR & MD) | (MU & MD);
+    uint32_t F = 0u, f = 0u;
+    (ising_bit<MODEL, L, LPC, WI, K>(F, f, bidx, rng, S, s0, s1, ML, MU, MD, T), ...);
+    cur[WI] = S ^ F;
+}
+
+template <int MODEL, int L, int LPC, int... WI>
+__device__ __forceinline__ void ising_row(const uint32_t (&up)[Row1<L>::W], uint32_t (&cur)[Row1<L>::W],
+                                          const uint32_t (&dn)[Row1<L>::W], int32_t &bidx,
+                                          const uint32_t *__restrict__ T, uint32_t chain, uint32_t g, int y,
+                                          uint32_t j, uint32_t k0, uint32_t k1, std::integer_sequence<int, WI...>)
+{
+    RowRng<L, LPC, 1> rng;
+    rng.fill(chain, g, y, j, k0, k1);
+    (ising_word<MODEL, L, LPC, WI>(up, cur, dn, bidx, rng, T,
+                                   std::make_integer_sequence<int, ((L - 32 * WI) < 32 ? (L - 32 * WI) : 32)>{}),
+     ...);
+}
+
+// Storage <-> packed row.  BYTE storage holds int8 +1 (0x01) / -1 (0xFF),
+// four sites per word; bit 1 of a byte is set exactly for -1.
+template <int L, int LAYOUT>
+__device__ __forceinline__ void load_row(const uint32_t *base, size_t stride, int y, uint32_t (&R)[Row1<L>::W])
+{
+    constexpr int W = Row1<L>::W;
+    if constexpr (LAYOUT == kLayoutBit) {
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            R[w] = base[((size_t)y * W + w) * stride];
+    } else {
+        constexpr int W8 = L / 4;
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            R[w] = 0u;
+#pragma unroll
+        for (int m = 0; m < W8; ++m) {
+            const uint32_t v = (base[((size_t)y * W8 + m) * stride] >> 1) & 0x01010101u; // -1 flags
+            const uint32_t nib = ((v * 0x00204081u) >> 21) & 0xFu;
+            R[(4 * m) / 32] |= (nib ^ 0xFu) << ((4 * m) % 32);
+        }
+    }
+}
+
+template <int L, int LAYOUT>
+__device__ __forceinline__ void store_row(uint32_t *base, size_t stride, int y, const uint32_t (&R)[Row1<L>::W])
+{
+    constexpr int W = Row1<L>::W;
+    if constexpr (LAYOUT == kLayoutBit) {
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            base[((size_t)y * W + w) * stride] = R[w];
+    } else {
+        constexpr int W8 = L / 4;
+#pragma unroll
+        for (int m = 0; m < W8; ++m) {
+            const uint32_t nib = (R[(4 * m) / 32] >> ((4 * m) % 32)) & 0xFu;
+            const uint32_t up1 = (nib * 0x00204081u) & 0x01010101u; // 1 in the bytes of +1 spins
+            base[((size_t)y * W8 + m) * stride] = 0xFFFFFFFFu ^ (up1 * 0xFEu); // 0x01 or 0xFF
+        }
+    }
+}
+
+// One q-state Potts site update: proposal among the q-1 other colours,
+// dE = (neighbours equal to old) - (neighbours equal to new) unsatisfied bonds.
+template <int L, int LPC, int W, int X>
+__device__ __forceinline__ void potts_site(const uint32_t (&up)[W], uint32_t (&cur)[W],
+                                           const uint32_t (&dn)[W], int32_t &b, const RowRng<L, LPC, 2> &rng,
+                                           const uint32_t *__restrict__ T, uint32_t q)
+{
+    const uint32_t wp = rng.template get<X, 0>();
+    const uint32_t r = min(rng.template get<X, 1>(), 0xFFFFFFFEu);
+    const uint32_t old = colour<L>(cur, X);
+    uint32_t nw = old + 1u + __umulhi(wp, q - 1u);
+    nw = nw >= q ? nw - q : nw;
+    const uint32_t cl = colour<L>(cur, (X + L - 1) % L);
+    const uint32_t cr = colour<L>(cur, (X + 1) % L);
+    const uint32_t cu = colour<L>(up, X);
+    const uint32_t cd = colour<L>(dn, X);
+    const int32_t n_old = (cl == old) + (cr == old) + (cu == old) + (cd == old);
+    const int32_t n_new = (cl == nw) + (cr == nw) + (cu == nw) + (cd == nw);
+    const int32_t dE = n_old - n_new;
+    const uint32_t t = T[b * 9 + dE + 4];
+    const bool acc = r < t;
+    cur[X / 4] ^= acc ? ((old ^ nw) << ((X % 4) * 8)) : 0u;
+    b += acc ? dE : 0;
+}
+
+template <int L, int LPC, int W, int... X>
+__device__ __forceinline__ void potts_row(const uint32_t (&up)[W], uint32_t (&cur)[W],
+                                          const uint32_t (&dn)[W], int32_t &b,
+                                          const uint32_t *__restrict__ T, uint32_t chain,
+                                          uint32_t g, int y, uint32_t j, uint32_t k0, uint32_t k1, uint32_t q,
+                                          std::integer_sequence<int, X...>)
+{
+    RowRng<L, LPC, 2> rng;
+    rng.fill(chain, g, y, j, k0, k1);
+    (potts_site<L, LPC, W, X>(up, cur, dn, b, rng, T, q), ...);
+}
+
+template <int MODEL, int L, int LAYOUT, bool TLDS, int LPC>
+__global__ __launch_bounds__(256) void lattice_sweeps(LatticeArgs a)
+{
+    constexpr int NC = Cols<MODEL>::value;
+    extern __shared__ uint32_t smem[];
+    uint32_t *lhist = smem;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < a.n_bins; i += blockDim.x)
+        lhist[i] = 0u;
+    const uint32_t *T = a.thresholds;
+    if constexpr (TLDS) {
+        uint32_t *ltab = smem + a.n_bins;
+        for (int i = tid; i < a.n_bins * NC; i += blockDim.x)
+            ltab[i] = a.thresholds[i];
+        T = ltab;
+    }
+    __syncthreads();
+
+    const int gt = blockIdx.x * blockDim.x + tid;
+    const int c = gt / LPC;                // chain of this lane
+    const uint32_t j = (uint32_t)(gt % LPC); // rank within the chain's lane group
+    const bool leader = j == 0u;
+    uint32_t *base = a.words + c;
+    const size_t stride = (size_t)a.c_pad;
+    const uint32_t chain = (uint32_t)(a.chain0 + c);
+    const bool counts = a.record && c < a.n_chains && leader;
+    int32_t b = a.bins[c];
+
+    if constexpr (MODEL == kPotts) {
+        constexpr int W = Geom<L, LAYOUT>::kWpr;
+        const uint32_t q = (uint32_t)a.q;
+        uint32_t up[W], cur[W], dn[W], nx[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            up[w] = base[((L - 1) * W + w) * stride];
+            cur[w] = base[(0 * W + w) * stride];
+            dn[w] = base[((1 % L) * W + w) * stride];
+            nx[w] = base[((2 % L) * W + w) * stride];
+        }
+        for (int s = 0; s < a.n_sweeps; ++s) {
+            const uint32_t g = a.g0 + (uint32_t)s;
+            for (int y = 0; y < L; ++y) {
+                potts_row<L, LPC, W>(up, cur, dn, b, T, chain, g, y, j, a.k0, a.k1, q,
+                                     std::make_integer_sequence<int, L>{});
+                const int yn = (y + 3) % L;
+                if (leader) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w)
+                        base[(y * W + w) * stride] = cur[w];
+                }
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    up[w] = cur[w];
+                    cur[w] = dn[w];
+                    dn[w] = nx[w];
+                    nx[w] = base[(yn * W + w) * stride];
+                }
+            }
+            if (counts)
+                atomicAdd(&lhist[b], 1u);
+        }
+    } else {
+        constexpr int W = Row1<L>::W;
+        uint32_t up[W], cur[W], dn[W], nx[W];
+        load_row<L, LAYOUT>(base, stride, L - 1, up);
+        load_row<L, LAYOUT>(base, stride, 0, cur);
+        load_row<L, LAYOUT>(base, stride, 1 % L, dn);
+        load_row<L, LAYOUT>(base, stride, 2 % L, nx);
+        int32_t bidx = b * NC; // row offset of the current bin in the threshold table
+        for (int s = 0; s < a.n_sweeps; ++s) {
+            const uint32_t g = a.g0 + (uint32_t)s;
+            for (int y = 0; y < L; ++y) {
+                ising_row<MODEL, L, LPC>(up, cur, dn, bidx, T, chain, g, y, j, a.k0, a.k1,
+                                         std::make_integer_sequence<int, W>{});
+                if (leader)
+                    store_row<L, LAYOUT>(base, stride, y, cur);
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    up[w] = cur[w];
+                    cur[w] = dn[w];
+                    dn[w] = nx[w];
+                }
+                load_row<L, LAYOUT>(base, stride, (y + 3) % L, nx);
+            }
+            if (counts)
+                atomicAdd(&lhist[bidx / NC], 1u);
+        }
+        b = bidx / NC;
+    }
+    if (leader)
+        a.bins[c] = b;
+    __syncthreads();
+    for (int i = tid; i < a.n_bins; i += blockDim.x) {
+        const uint32_t v = lhist[i];
+        if (v)
+            atomicAdd(&a.hist[i], (unsigned long long)v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launch of one compiled variant.  `threads` per block (64..256); LPC lanes
+// per chain, so a block holds threads / LPC chains.
+// ---------------------------------------------------------------------------
+template <int MODEL, int L, int LAYOUT, int LPC>
+static hipError_t launch_variant(int threads, const LatticeArgs &a, hipStream_t s)
+{
+    constexpr int NC = Cols<MODEL>::value;
+    const long lanes = (long)a.c_pad * LPC;
+    if (threads < 64 || threads > 256 || lanes % threads)
+        return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(lanes / threads)), block(threads);
+    size_t lds = (size_t)a.n_bins * 4u;
+    if (a.table_in_lds) {
+        lds += (size_t)a.n_bins * NC * 4u;
+        auto k = lattice_sweeps<MODEL, L, LAYOUT, true, LPC>;
+        if (lds > 65536u) {
+            hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess)
+                return e;
+        }
+        hipLaunchKernelGGL(k, grid, block, lds, s, a);
+    } else {
+        auto k = lattice_sweeps<MODEL, L, LAYOUT, false, LPC>;
+        hipLaunchKernelGGL(k, grid, block, lds, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <int MODEL, int L, int LAYOUT>
+static hipError_t launch_lpc(int lpc, int threads, const LatticeArgs &a, hipStream_t s)
+{
+    switch (lpc) {
+    case 1: return launch_variant<MODEL, L, LAYOUT, 1>(threads, a, s);
+    case 2: return launch_variant<MODEL, L, LAYOUT, 2>(threads, a, s);
+    case 4: return launch_variant<MODEL, L, LAYOUT, 4>(threads, a, s);
+    case 16: return launch_variant<MODEL, L, LAYOUT, 16>(threads, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int MODEL, int LAYOUT>
+static hipError_t launch_model(int L, int lpc, int threads, const LatticeArgs &a, hipStream_t s)
+{
+    switch (L) {
+    case 4: return launch_lpc<MODEL, 4, LAYOUT>(lpc, threads, a, s);
+    case 8: return launch_lpc<MODEL, 8, LAYOUT>(lpc, threads, a, s);
+    case 16: return launch_lpc<MODEL, 16, LAYOUT>(lpc, threads, a, s);
+    case 24: return launch_lpc<MODEL, 24, LAYOUT>(lpc, threads, a, s);
+    case 32: return launch_lpc<MODEL, 32, LAYOUT>(lpc, threads, a, s);
+    case 48: return launch_lpc<MODEL, 48, LAYOUT>(lpc, threads, a, s);
+    case 64: return launch_lpc<MODEL, 64, LAYOUT>(lpc, threads, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+} // namespace muca

@@ -44,8 +44,9 @@ __host__ __device__ inline int words_per_row(int L, int layout) { return layout 
 
 // Launchers (lattice.hip).
 hipError_t launch_lattice_init(const LatticeInitArgs &a, hipStream_t s);
-hipError_t launch_lattice_sweeps(int model, int L, int layout, int chains_per_block, int n_cols,
-                                 const LatticeArgs &a, hipStream_t s);
+// threads per block in {64, 128, 256}; lpc lanes per chain in {1, 2, 4, 16}
+hipError_t launch_lattice_sweeps(int model, int L, int layout, int lpc, int threads, const LatticeArgs &a,
+                                 hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t s);
 bool lattice_size_supported(int L);
 

@@ -29,13 +29,23 @@ struct Words4 {
     uint32_t w[4];
 };
 
+// Rounds 0 and 1 keep plain XORs so that wave-uniform inputs can stay on
+// the scalar unit; later rounds use one gfx950 three-input bitop3 (truth
+// table 0x96 = a ^ b ^ c) per output word.
+template <int R>
 __device__ __forceinline__ void philox_round(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3,
                                              uint32_t k0, uint32_t k1)
 {
     const uint64_t p0 = (uint64_t)kPhiloxM0 * x0;
     const uint64_t p1 = (uint64_t)kPhiloxM1 * x2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    uint32_t n0, n2;
+    if constexpr (R < 2) {
+        n0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        n2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    } else {
+        n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), x1, k0, 0x96);
+        n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), x3, k1, 0x96);
+    }
     x1 = (uint32_t)p1;
     x3 = (uint32_t)p0;
     x0 = n0;
@@ -45,10 +55,16 @@ __device__ __forceinline__ void philox_round(uint32_t &x0, uint32_t &x1, uint32_
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1)
 {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        philox_round(c0, c1, c2, c3, k0 + (uint32_t)r * kPhiloxW0, k1 + (uint32_t)r * kPhiloxW1);
-    }
+    philox_round<0>(c0, c1, c2, c3, k0, k1);
+    philox_round<1>(c0, c1, c2, c3, k0 + 1u * kPhiloxW0, k1 + 1u * kPhiloxW1);
+    philox_round<2>(c0, c1, c2, c3, k0 + 2u * kPhiloxW0, k1 + 2u * kPhiloxW1);
+    philox_round<3>(c0, c1, c2, c3, k0 + 3u * kPhiloxW0, k1 + 3u * kPhiloxW1);
+    philox_round<4>(c0, c1, c2, c3, k0 + 4u * kPhiloxW0, k1 + 4u * kPhiloxW1);
+    philox_round<5>(c0, c1, c2, c3, k0 + 5u * kPhiloxW0, k1 + 5u * kPhiloxW1);
+    philox_round<6>(c0, c1, c2, c3, k0 + 6u * kPhiloxW0, k1 + 6u * kPhiloxW1);
+    philox_round<7>(c0, c1, c2, c3, k0 + 7u * kPhiloxW0, k1 + 7u * kPhiloxW1);
+    philox_round<8>(c0, c1, c2, c3, k0 + 8u * kPhiloxW0, k1 + 8u * kPhiloxW1);
+    philox_round<9>(c0, c1, c2, c3, k0 + 9u * kPhiloxW0, k1 + 9u * kPhiloxW1);
     Words4 o;
     o.w[0] = c0;
     o.w[1] = c1;

@@ -102,10 +102,23 @@ int muca_geometry(const muca_config *c, Geometry *g)
         return muca_fail(MUCA_E_ARG, "Potts has no bit layout");
     g->n_bins = (c->hi - c->lo) / g->step + 1;
     g->wpr = words_per_row(c->L, g->layout);
-    int cpb = c->chains_per_block ? c->chains_per_block : 64;
-    if (cpb != 64 && cpb != 128 && cpb != 256)
-        return muca_fail(MUCA_E_ARG, "chains_per_block %d not in {64, 128, 256}", cpb);
-    while (g->c_pad % cpb)
+    int lpc = c->lanes_per_chain;
+    if (lpc == 0) {
+        // enough lanes to give every SIMD of the chip a wavefront, at most 16
+        lpc = 16;
+        while (lpc > 1 && (long)g->c_pad * lpc > 65536L)
+            lpc /= lpc == 16 ? 4 : 2;
+    }
+    if (lpc != 1 && lpc != 2 && lpc != 4 && lpc != 16)
+        return muca_fail(MUCA_E_ARG, "lanes_per_chain %d not in {1, 2, 4, 16}", lpc);
+    g->lpc = lpc;
+    // default: 256-thread blocks, so a block that stages the threshold table
+    // in LDS (one block per CU) still carries four wavefronts of work
+    int cpb = c->chains_per_block ? c->chains_per_block * lpc : 256;
+    if (c->chains_per_block && (c->chains_per_block < 1 || cpb > 256 || cpb % 64))
+        return muca_fail(MUCA_E_ARG, "chains_per_block %d x lanes_per_chain %d must be 64, 128 or 256 threads",
+                         c->chains_per_block, lpc);
+    while (((long)g->c_pad * lpc) % cpb)
         cpb /= 2;
     g->cpb = cpb;
     const size_t hist_lds = (size_t)g->n_bins * 4u;
@@ -505,7 +518,7 @@ int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s)
         return muca_polymer_enqueue(r, sweeps, record, s);
     const Geometry &g = r->g;
     // keep each launch's per-block u32 LDS counts below 2^32
-    const int64_t max_chunk = std::max<int64_t>(1, (int64_t)(0xFFFFFFFFll / g.cpb) - 1);
+    const int64_t max_chunk = std::max<int64_t>(1, (int64_t)(0xFFFFFFFFll / (g.cpb / g.lpc)) - 1);
     int64_t done = 0;
     while (done < sweeps) {
         const int64_t n = std::min<int64_t>(sweeps - done, std::min<int64_t>(max_chunk, 1 << 30));
@@ -525,7 +538,7 @@ int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s)
         a.record = record ? 1 : 0;
         a.table_in_lds = g.table_in_lds ? 1 : 0;
         a.chain0 = 0;
-        HIP_OR_POISON(r, launch_lattice_sweeps(g.model, g.L, g.layout, g.cpb, g.n_cols, a, s));
+        HIP_OR_POISON(r, launch_lattice_sweeps(g.model, g.L, g.layout, g.lpc, g.cpb, a, s));
         r->sweep += (uint32_t)n;
         done += n;
     }

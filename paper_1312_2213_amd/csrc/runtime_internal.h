@@ -16,7 +16,8 @@ struct Geometry {
     int n_bins, n_cols;  // threshold table is n_bins x n_cols (polymer: n_bins x n_bins)
     int layout, wpr;     // lattice storage
     int c_pad;           // chains rounded up to a multiple of 64
-    int cpb;             // chains per block
+    int cpb;             // threads per block
+    int lpc;             // lanes per chain
     bool table_in_lds;
     size_t off_words, off_bins, off_values, off_table, off_hist, off_energy;
     size_t ws_bytes;

@@ -37,7 +37,7 @@ class muca_config(ctypes.Structure):
                 ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double),
                 ("lj_eps", ctypes.c_double), ("lj_sigma", ctypes.c_double), ("lj_rcut", ctypes.c_double),
                 ("fene_k", ctypes.c_double), ("fene_r0", ctypes.c_double), ("fene_R", ctypes.c_double),
-                ("step", ctypes.c_float), ("reserved", ctypes.c_int32)]
+                ("step", ctypes.c_float), ("lanes_per_chain", ctypes.c_int32)]
 
 
 class muca_iter_stats(ctypes.Structure):

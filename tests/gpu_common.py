@@ -7,12 +7,12 @@ from oracle import oracle as orc
 MODEL_ID = {"ising": orc.ISING, "potts": orc.POTTS, "muma": orc.MUMA}
 
 
-def pair(model, L, chains, seed, q=2, lo=None, hi=None, beta=0.5, layout=0, cpb=0, tlds=-1):
+def pair(model, L, chains, seed, q=2, lo=None, hi=None, beta=0.5, layout=0, cpb=0, tlds=-1, lpc=0):
     import torch  # noqa: F401
     from paper_1312_2213_amd import muca
     o = orc.LatticeRun(MODEL_ID[model], L, chains, seed, q=q, lo=lo, hi=hi,
                        beta=beta if model == "muma" else 0.0)
-    kw = dict(layout=layout, chains_per_block=cpb, table_in_lds=tlds)
+    kw = dict(layout=layout, chains_per_block=cpb, table_in_lds=tlds, lanes_per_chain=lpc)
     if lo is not None:
         kw["lo"] = lo
     if hi is not None:

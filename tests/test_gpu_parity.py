@@ -97,18 +97,22 @@ def test_single_chain_and_ragged_tail():
         assert_same_state(o, g)
 
 
-def test_invariant_to_launch_shape_and_table_placement():
-    ref = None
-    for cpb in (64, 128, 256):
-        for tlds in (0, 1):
-            o, g = pair("ising", 16, 256, seed=4, cpb=cpb, tlds=tlds)
-            g.run_iteration(25)
-            g.merge_update()
-            s, b, _ = g.chain_state()
-            cur = (g.last_hist().tobytes(), s.tobytes(), b.tobytes())
-            if ref is None:
-                ref = cur
-            assert cur == ref, (cpb, tlds)
+@pytest.mark.parametrize("model,layout,q", [("ising", 1, 2), ("ising", 2, 2), ("muma", 1, 2), ("potts", 2, 6)])
+def test_invariant_to_launch_shape_lanes_and_table_placement(model, layout, q):
+    """Every compiled variant (lanes per chain, threads per block, threshold
+    table in LDS or global memory) gives the identical Markov chains."""
+    o, _ = pair(model, 16, 128, seed=4, q=q, layout=layout)
+    H = o.sweeps(25)
+    for lpc in (1, 2, 4, 16):
+        for threads in (64, 256):
+            for tlds in (0, 1):
+                cpb = max(1, threads // lpc)
+                _, g = pair(model, 16, 128, seed=4, q=q, layout=layout, cpb=cpb, tlds=tlds, lpc=lpc)
+                g.run_iteration(25)
+                g.merge_update()
+                s, b, _ = g.chain_state()
+                assert np.array_equal(g.last_hist(), H), (lpc, threads, tlds)
+                assert np.array_equal(s, o.spins) and np.array_equal(b, o.bins()), (lpc, threads, tlds)
 
 
 def test_chunked_iteration_equals_one_piece():
