@@ -39,6 +39,26 @@ struct LatticeInitArgs {
     int32_t model, layout;
 };
 
+// Arguments of one polymer sweep launch (one chain per wavefront).
+struct PolymerArgs {
+    float4 *pos;                // [c_pad][64] bead positions (w unused)
+    double *bond;               // [c_pad][64] energy of bond (j, j + 1)
+    double *energy;             // [c_pad] running energy
+    int32_t *bins;              // [c_pad]
+    const uint32_t *thresholds; // [n_bins][n_bins]
+    unsigned long long *hist;   // [n_bins]
+    uint32_t k0, k1, g0;
+    int32_t n_sweeps, n_chains, c_pad, n_bins, n_beads, record, chains_per_block;
+    float step;
+};
+
+// Potential constants, each evaluated on the host once in a fixed order.
+struct PolymerConsts {
+    double lj_eps, lj_sigma, lj_rcut, lj_shift, fene_pref, fene_r0, fene_R, x_lo, x_hi, scale;
+};
+
+hipError_t launch_polymer_sweeps(const PolymerArgs &a, const PolymerConsts &k, hipStream_t s);
+
 // Number of 32-bit words per lattice row.
 __host__ __device__ inline int words_per_row(int L, int layout) { return layout == kLayoutBit ? (L + 31) / 32 : (L + 3) / 4; }
 

@@ -410,8 +410,10 @@ static int upload_thresholds(muca_run *r)
 
 int muca_rebuild_thresholds(muca_run *r)
 {
-    if (r->g.model == kPolymer)
+    if (r->g.model == kPolymer) {
+        muca_polymer_build(r);
         return muca_polymer_upload(r);
+    }
     build_lattice_thresholds(&r->cfg, r->g, r->lnW.data(), r->T.data());
     return upload_thresholds(r);
 }

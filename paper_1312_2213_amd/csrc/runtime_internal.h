@@ -60,6 +60,7 @@ double muca_flatness(int B, const uint8_t *m, const uint64_t *H);
 // polymer.cpp
 int muca_polymer_geometry(const muca_config *c, muca::Geometry *g);
 int muca_polymer_init(muca_run *r, const float *h_pos);
+void muca_polymer_build(muca_run *r);
 int muca_polymer_upload(muca_run *r);
 int muca_polymer_enqueue(muca_run *r, int64_t sweeps, bool record, hipStream_t s);
 int muca_polymer_state(muca_run *r, int32_t chain0, int32_t count, float *pos, int32_t *bins,

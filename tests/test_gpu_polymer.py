@@ -1,0 +1,73 @@
+"""GPU polymer path against the oracle: same initial conformations, same
+Philox streams and thresholds.  Histograms, bins and float positions must be
+identical; running energies agree to 1e-12 (FP64 terms summed in the same
+tree order; the device and host logarithms may differ in the last bit)."""
+import numpy as np
+import pytest
+
+from synth import polymer_walk
+
+pytestmark = pytest.mark.gpu
+
+
+def pair(n_beads, chains, seed, lnw=None):
+    import torch  # noqa: F401
+    from oracle import oracle as orc
+    from paper_1312_2213_amd import muca
+    pos = polymer_walk(n_beads, chains, seed)
+    o = orc.PolymerRun(n_beads=n_beads, n_chains=chains, seed=seed, pos=pos)
+    cfg = muca.muca_config_default("polymer", 0, 2, chains, seed, n_beads=n_beads)
+    g = muca.Run(cfg, positions=pos)
+    if lnw is not None:
+        o.lnW = np.array(lnw, np.float64)
+        g.set_lnw(lnw)
+    return o, g
+
+
+def check_state(o, g, chains=None):
+    pos, bins, E = g.chain_state()
+    sel = range(o.n_chains) if chains is None else chains
+    for c in sel:
+        assert bins[c] == o.bin[c], f"chain {c}: bin {bins[c]} vs {o.bin[c]}"
+        assert np.array_equal(pos[c], o.pos[c]), f"chain {c}: positions differ"
+        assert abs(E[c] - o.E[c]) <= 1e-12 * max(1.0, abs(o.E[c])), f"chain {c}: E {E[c]} vs {o.E[c]}"
+
+
+def test_polymer_initial_state():
+    o, g = pair(40, 70, 5)
+    pos, bins, E = g.chain_state()
+    assert np.array_equal(E, o.E) and np.array_equal(bins, o.bin)
+
+
+def test_polymer_sweeps_with_weights():
+    cent = -200.0 + 0.1 * (np.arange(2500) + 0.5)
+    o, g = pair(40, 70, 6, lnw=-0.7 * cent)
+    H = o.sweeps(20)
+    g.run_iteration(20)
+    g.merge_update()
+    assert np.array_equal(g.last_hist(), H)
+    check_state(o, g)
+
+
+def test_polymer_iterations_with_recursion():
+    o, g = pair(24, 65, 7)
+    for it in range(3):
+        H = o.sweeps(15)
+        o.advance(15)
+        o.merge_update(H)
+        g.run_iteration(15)
+        st = g.merge_update()
+        assert np.array_equal(g.last_hist(), H), it
+        assert np.allclose(g.lnw(), o.lnW, rtol=0, atol=1e-12), it
+    check_state(o, g)
+
+
+def test_polymer_full_size_sampled():
+    """The polymer workload's shape: N = 40, 4096 chains, one chain per wave."""
+    cent = -200.0 + 0.1 * (np.arange(2500) + 0.5)
+    o, g = pair(40, 4096, 5, lnw=-0.3 * cent)
+    g.run_iteration(2)
+    g.merge_update()
+    H = o.sweeps(2)
+    assert np.array_equal(g.last_hist(), H)
+    check_state(o, g, chains=(0, 1, 63, 64, 2048, 4095))
