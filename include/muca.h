@@ -142,15 +142,40 @@ int muca_merge_update(muca_run *run, muca_iter_stats *out);
  * Potts energies are E_unsat - 2N; polymer bins use their centres. */
 int muca_reweight(const muca_run *run, const double *betas, int32_t n, double *out);
 
-/* One persistent launch for several runs (mixed models, L, q, ensembles):
- * equivalent to muca_run_iteration(runs[i], sweeps[i]) for every i, with
- * identical results.  d_batch_ws is caller-owned device memory of
- * muca_batch_workspace_bytes(n) bytes.  When graph != 0 the launch is
- * captured once in a hipGraph and relaunched on later calls with the same
- * runs. */
-int muca_batch_workspace_bytes(int32_t n_runs, uint64_t *bytes);
-int muca_batch_run_iteration(muca_run *const *runs, int32_t n_runs, const int64_t *sweeps,
-                             void *d_batch_ws, uint64_t batch_ws_bytes, int32_t graph, void *stream);
+/* Batched iterations (one persistent launch for several lattice runs of
+ * mixed model, L, q, ensemble and layout).  The runs' chains are cut into
+ * work items of 256 / lanes_per_chain chains that a grid sized to the chip
+ * takes longest first from an atomic queue; each work item runs exactly the
+ * sweep code of muca_run_iteration, so every run's histogram and chains are
+ * bit-identical to plain launches.
+ *   muca_batch_workspace_bytes: device bytes for up to max_runs runs and
+ *     max_items work items.
+ *   muca_batch_create: lanes_per_chain 4 or 16; use_graph != 0 captures
+ *     [descriptor upload, queue reset, persistent kernel] in a hipGraph once
+ *     and relaunches it (requires a non-null stream).  d_ws is caller-owned
+ *     (256-byte aligned); the handle owns a small pinned host buffer.
+ *   muca_batch_run_iteration: equivalent to muca_run_iteration(runs[i],
+ *     sweeps[i]) for every i; returns after the launch has completed.
+ *     MUCA_E_ARG for polymer runs, L outside {8,16,24,32,48,64}, a run given
+ *     twice, or capacity exceeded. */
+typedef struct muca_batch muca_batch;
+int muca_batch_workspace_bytes(int32_t max_runs, int32_t max_items, uint64_t *bytes);
+int muca_batch_create(int32_t max_runs, int32_t max_items, int32_t lanes_per_chain, int32_t use_graph,
+                      void *d_ws, uint64_t ws_bytes, muca_batch **out);
+int muca_batch_run_iteration(muca_batch *batch, muca_run *const *runs, int32_t n_runs, const int64_t *sweeps,
+                             void *stream);
+void muca_batch_free(muca_batch *batch);
+
+/* Autotuner: times `sweeps` sweeps of every compiled variant of cfg (layout,
+ * lanes per chain, chains per block, threshold table in LDS or global) in
+ * the caller's workspace d_ws and returns the fastest in *best (time per
+ * sweep in *best_ms_per_sweep, -1 when taken from the cache).  A candidate
+ * whose histogram, spins or bins differ from the first candidate's is
+ * rejected.  With MUCA_AUTOTUNE_CACHE set to a file path, results are read
+ * from / written to that JSON file, keyed by GPU architecture and shape.
+ * The workspace must hold the largest candidate (layout BYTE for Ising). */
+int muca_autotune(const muca_config *cfg, void *d_ws, uint64_t ws_bytes, int64_t sweeps, void *stream,
+                  muca_config *best, double *best_ms_per_sweep);
 
 /* Accessors (host copies; synchronise the run's stream). */
 int muca_sizes(const muca_run *run, int32_t *n_bins, int32_t *n_cols, int32_t *n_sites);

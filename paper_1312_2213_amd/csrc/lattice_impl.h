@@ -268,11 +268,18 @@ __device__ __forceinline__ void potts_row(const uint32_t (&up)[W], uint32_t (&cu
     (potts_site<L, LPC, W, X>(up, cur, dn, b, rng, T, q), ...);
 }
 
+// ---------------------------------------------------------------------------
+// One block of chains: threads [0, blockDim) handle chains
+// [c_first, c_first + blockDim / LPC) of the instance described by `a`.
+// The threshold table is staged into LDS (TLDS) and the block's histogram is
+// accumulated in LDS, then added to the instance's global histogram.
+// Used by the plain kernel (one launch per instance) and by the persistent
+// batched kernel (one block per work item).
+// ---------------------------------------------------------------------------
 template <int MODEL, int L, int LAYOUT, bool TLDS, int LPC>
-__global__ __launch_bounds__(256) void lattice_sweeps(LatticeArgs a)
+__device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, uint32_t *smem)
 {
     constexpr int NC = Cols<MODEL>::value;
-    extern __shared__ uint32_t smem[];
     uint32_t *lhist = smem;
     const int tid = threadIdx.x;
     for (int i = tid; i < a.n_bins; i += blockDim.x)
@@ -286,9 +293,8 @@ __global__ __launch_bounds__(256) void lattice_sweeps(LatticeArgs a)
     }
     __syncthreads();
 
-    const int gt = blockIdx.x * blockDim.x + tid;
-    const int c = gt / LPC;                // chain of this lane
-    const uint32_t j = (uint32_t)(gt % LPC); // rank within the chain's lane group
+    const int c = c_first + tid / LPC;       // chain of this lane
+    const uint32_t j = (uint32_t)(tid % LPC); // rank within the chain's lane group
     const bool leader = j == 0u;
     uint32_t *base = a.words + c;
     const size_t stride = (size_t)a.c_pad;
@@ -365,6 +371,13 @@ __global__ __launch_bounds__(256) void lattice_sweeps(LatticeArgs a)
         if (v)
             atomicAdd(&a.hist[i], (unsigned long long)v);
     }
+}
+
+template <int MODEL, int L, int LAYOUT, bool TLDS, int LPC>
+__global__ __launch_bounds__(256) void lattice_sweeps(LatticeArgs a)
+{
+    extern __shared__ uint32_t smem[];
+    sweep_block<MODEL, L, LAYOUT, TLDS, LPC>(a, (int)(blockIdx.x * (blockDim.x / LPC)), smem);
 }
 
 // ---------------------------------------------------------------------------

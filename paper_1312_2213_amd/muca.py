@@ -64,8 +64,11 @@ def _load():
         "muca_thermalize": (ctypes.c_int, [vp, i64, vp]),
         "muca_merge_update": (ctypes.c_int, [vp, P(muca_iter_stats)]),
         "muca_reweight": (ctypes.c_int, [vp, vp, i32, vp]),
-        "muca_batch_workspace_bytes": (ctypes.c_int, [i32, P(ctypes.c_uint64)]),
-        "muca_batch_run_iteration": (ctypes.c_int, [P(vp), i32, P(ctypes.c_int64), vp, u64, i32, vp]),
+        "muca_batch_workspace_bytes": (ctypes.c_int, [i32, i32, P(ctypes.c_uint64)]),
+        "muca_batch_create": (ctypes.c_int, [i32, i32, i32, i32, vp, u64, P(vp)]),
+        "muca_batch_run_iteration": (ctypes.c_int, [vp, P(vp), i32, P(ctypes.c_int64), vp]),
+        "muca_batch_free": (None, [vp]),
+        "muca_autotune": (ctypes.c_int, [P(muca_config), vp, u64, i64, vp, P(muca_config), P(ctypes.c_double)]),
         "muca_sizes": (ctypes.c_int, [vp, P(i32), P(i32), P(i32)]),
         "muca_get_lnw": (ctypes.c_int, [vp, vp, i32]),
         "muca_get_last_hist": (ctypes.c_int, [vp, vp, i32]),
@@ -88,7 +91,7 @@ def _load():
 LIB = _load()
 EXPORTED = ("muca_config_default", "muca_workspace_bytes", "muca_init", "muca_run_iteration",
             "muca_thermalize", "muca_merge_update", "muca_reweight", "muca_batch_workspace_bytes",
-            "muca_batch_run_iteration", "muca_sizes", "muca_get_lnw", "muca_get_last_hist",
+            "muca_batch_create", "muca_batch_run_iteration", "muca_batch_free", "muca_autotune", "muca_sizes", "muca_get_lnw", "muca_get_last_hist",
             "muca_get_thresholds", "muca_get_chain_state", "muca_set_lnw", "muca_set_thresholds",
             "muca_checkpoint", "muca_restore", "muca_free", "muca_last_error")
 
@@ -231,20 +234,51 @@ class Run:
             pass
 
 
-def muca_batch_run_iteration(runs, sweeps, batch_ws=None, graph: bool = False, stream=None):
-    """One persistent launch over several runs; batch_ws is a uint8 CUDA tensor."""
+class Batch:
+    """Persistent batched launches over several lattice runs (workspace tensor kept alive)."""
+
+    def __init__(self, max_runs: int, max_items: int = 8192, lanes_per_chain: int = 4,
+                 use_graph: bool = True, device="cuda"):
+        import torch
+        n = ctypes.c_uint64(0)
+        _check(LIB.muca_batch_workspace_bytes(max_runs, max_items, ctypes.byref(n)))
+        self.workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.handle = ctypes.c_void_p()
+        _check(LIB.muca_batch_create(max_runs, max_items, lanes_per_chain, int(bool(use_graph)),
+                                     ctypes.c_void_p(aligned), n.value, ctypes.byref(self.handle)))
+
+    def run_iteration(self, runs, sweeps, stream=None):
+        n = len(runs)
+        handles = (ctypes.c_void_p * n)(*[r.handle.value for r in runs])
+        sw = (ctypes.c_int64 * n)(*[int(s) for s in (sweeps if np.ndim(sweeps) else [sweeps] * n)])
+        _check(LIB.muca_batch_run_iteration(self.handle, handles, n, sw, _stream_handle(stream)))
+
+    def free(self):
+        if self.handle:
+            LIB.muca_batch_free(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def muca_autotune(cfg: muca_config, sweeps: int, stream=None):
+    """Fastest compiled variant of cfg (timed on the device); returns (config, ms per sweep)."""
     import torch
-    n = len(runs)
-    need = ctypes.c_uint64(0)
-    _check(LIB.muca_batch_workspace_bytes(n, ctypes.byref(need)))
-    if batch_ws is None or batch_ws.numel() < need.value + 256:
-        batch_ws = torch.empty(need.value + 256, dtype=torch.uint8, device="cuda")
-    base = batch_ws.data_ptr()
-    aligned = (base + 255) // 256 * 256
-    handles = (ctypes.c_void_p * n)(*[r.handle.value for r in runs])
-    sw = (ctypes.c_int64 * n)(*[int(s) for s in (sweeps if np.ndim(sweeps) else [sweeps] * n)])
-    _check(LIB.muca_batch_run_iteration(handles, n, sw, ctypes.c_void_p(aligned), need.value,
-                                        int(bool(graph)), _stream_handle(stream)))
-    for r, s in zip(runs, sw):
-        pass
-    return batch_ws
+    big = muca_config.from_buffer_copy(cfg)
+    if big.model in (MUCA_ISING, MUCA_MUMA) and big.layout == MUCA_LAYOUT_AUTO:
+        big.layout = MUCA_LAYOUT_BYTE
+    n = muca_workspace_bytes(big)
+    ws = torch.empty(n + 256, dtype=torch.uint8, device="cuda")
+    aligned = (ws.data_ptr() + 255) // 256 * 256
+    best = muca_config()
+    ms = ctypes.c_double(0.0)
+    rc = LIB.muca_autotune(ctypes.byref(cfg), ctypes.c_void_p(aligned), n, int(sweeps),
+                           _stream_handle(stream), ctypes.byref(best), ctypes.byref(ms))
+    _check(rc)
+    torch.cuda.synchronize()
+    return best, ms.value

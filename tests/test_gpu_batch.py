@@ -1,0 +1,114 @@
+"""Batched persistent launches (one launch for runs of mixed model, L, q,
+ensemble and layout) must reproduce plain per-run launches bit for bit,
+graph replays included; the autotuner returns a valid, result-preserving
+variant."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+MIX = [  # (model, L, q, chains, seed, layout, sweeps)
+    ("ising", 16, 2, 130, 41, 1, 12),
+    ("ising", 24, 2, 64, 42, 2, 7),
+    ("muma", 32, 2, 100, 43, 1, 5),
+    ("potts", 16, 8, 70, 44, 2, 9),
+    ("potts", 48, 3, 64, 45, 2, 2),
+    ("ising", 64, 2, 256, 46, 1, 3),
+    ("muma", 8, 2, 33, 47, 2, 20),
+]
+
+
+def make(spec):
+    from paper_1312_2213_amd import muca
+    model, L, q, chains, seed, layout, _ = spec
+    kw = dict(layout=layout)
+    if model == "muma":
+        kw["beta"] = 0.5
+    return muca.Run(muca.muca_config_default(model, L, q, chains, seed, **kw))
+
+
+def snapshot(r):
+    s, b, _ = r.chain_state()
+    return r.last_hist().copy(), r.lnw().copy(), s, b
+
+
+@pytest.mark.parametrize("graph,lpc", [(True, 4), (False, 4), (True, 16)])
+def test_batched_equals_plain(graph, lpc):
+    import torch
+    from paper_1312_2213_amd import muca
+    stream = torch.cuda.Stream()
+    plain = [make(s) for s in MIX]
+    batched = [make(s) for s in MIX]
+    batch = muca.Batch(len(MIX), lanes_per_chain=lpc, use_graph=graph)
+    sweeps = [s[-1] for s in MIX]
+    for it in range(4):
+        print(f"  iteration {it}", flush=True)
+        for r, sw in zip(plain, sweeps):
+            r.run_iteration(sw)
+            r.merge_update()
+        with torch.cuda.stream(stream):
+            batch.run_iteration(batched, sweeps, stream=stream)
+        for r in batched:
+            r.merge_update()
+        # eager device work between graph replays
+        torch.cuda.synchronize()
+        for k, (a, b) in enumerate(zip(plain, batched)):
+            sa, sb = snapshot(a), snapshot(b)
+            assert np.array_equal(sa[0], sb[0]), (it, k, "histogram")
+            assert np.array_equal(sa[1], sb[1]), (it, k, "lnW")
+            assert np.array_equal(sa[2], sb[2]) and np.array_equal(sa[3], sb[3]), (it, k, "chains")
+
+
+def test_batched_subset_and_regrouping():
+    """Runs can join and leave between rounds (the serving pattern)."""
+    import torch
+    from paper_1312_2213_amd import muca
+    stream = torch.cuda.Stream()
+    plain = [make(s) for s in MIX[:4]]
+    batched = [make(s) for s in MIX[:4]]
+    batch = muca.Batch(8, lanes_per_chain=4, use_graph=True)
+    groups = [[0, 1], [0, 1, 2, 3], [2, 3], [1, 3]]
+    for it, grp in enumerate(groups):
+        for k in grp:
+            plain[k].run_iteration(MIX[k][-1])
+            plain[k].merge_update()
+        with torch.cuda.stream(stream):
+            batch.run_iteration([batched[k] for k in grp], [MIX[k][-1] for k in grp], stream=stream)
+        for k in grp:
+            batched[k].merge_update()
+    for a, b in zip(plain, batched):
+        sa, sb = snapshot(a), snapshot(b)
+        assert all(np.array_equal(x, y) for x, y in zip(sa, sb))
+
+
+def test_batch_rejects_polymer_and_duplicates():
+    from paper_1312_2213_amd import muca
+    from synth import polymer_walk
+    p = muca.Run(muca.muca_config_default("polymer", 0, 2, 4, 1, n_beads=8), positions=polymer_walk(8, 4, 1))
+    r = make(MIX[0])
+    batch = muca.Batch(4, use_graph=False)
+    with pytest.raises(muca.MucaError):
+        batch.run_iteration([p], [1])
+    with pytest.raises(muca.MucaError):
+        batch.run_iteration([r, r], [1, 1])
+
+
+def test_autotune_returns_valid_variant(tmp_path, monkeypatch):
+    from paper_1312_2213_amd import muca
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("MUCA_AUTOTUNE_CACHE", str(cache))
+    cfg = muca.muca_config_default("ising", 32, 2, 512, 3)
+    best, ms = muca.muca_autotune(cfg, 10)
+    assert ms > 0 and best.lanes_per_chain in (1, 2, 4, 16) and best.layout in (1, 2)
+    assert cache.exists() and "gfx950" in cache.read_text()
+    again, ms2 = muca.muca_autotune(cfg, 10)
+    assert ms2 == -1.0 and (again.layout, again.lanes_per_chain, again.chains_per_block) == \
+        (best.layout, best.lanes_per_chain, best.chains_per_block)
+    # the tuned variant still reproduces the default variant's chains
+    a = muca.Run(cfg)
+    b = muca.Run(best)
+    for r in (a, b):
+        r.run_iteration(7)
+        r.merge_update()
+    assert np.array_equal(a.last_hist(), b.last_hist())
+    assert np.array_equal(a.chain_state()[0], b.chain_state()[0])
