@@ -1,18 +1,23 @@
 #!/usr/bin/env python3
-"""Benchmark of the multicanonical hot path on one MI355X.
+"""Benchmarks of the multicanonical hot path on one MI355X.
 
-Workload: plain MUCA, 2D Ising L = 64 (periodic), bit-packed spins, 4096
-chains, seed 2, lnW in FP64 and uint32 acceptance thresholds, 10^4 sweeps per
-iteration.  One step = one MUCA iteration: the sweep kernel over all chains
-(with the LDS/atomic histogram merge) followed by muca_merge_update (FP64
-accumulated-statistics recursion, flatness test, threshold rebuild and
-upload).  Inputs (spins, weights) are resident in HBM before the timed
-region.
+Default workload (the headline line): plain MUCA, 2D Ising L = 64 periodic,
+bit-packed spins, 4096 chains, seed 2, lnW in FP64 and uint32 acceptance
+thresholds, 10^4 sweeps per iteration.  One step = one MUCA iteration: the
+sweep kernel over all chains (LDS + atomic histogram merge) followed by
+muca_merge_update (FP64 accumulated-statistics recursion, flatness test,
+threshold rebuild and upload).  Inputs are resident in HBM before the timed
+region.  The line also carries:
+  roofline      the sweep kernel's figures (HIP-event duration on its stream);
+  cpu_baseline  the single-threaded C oracle on a bounded sample;
+  batched_vs_plain  the batched workload (q=8 Potts L in {16,24,32,48} x 2048
+                chains + 4 MUMA Ising L=32 x 512 chains at beta = 0.5): wall
+                time of one persistent hipGraph launch per round against the
+                same instances run one after another with plain launches.
 
-Prints one JSON line: attempts/s (every Metropolis attempt counts, accepted or
-not), the sweep kernel's roofline figures (HIP-event duration on the launch
-stream), and the single-threaded CPU oracle timed on a bounded sample of the
-same workload.
+Other modes (--workload): "batched" (time to flat, batched vs plain),
+"serving" (200 Poisson requests, p50/p99 time to flat), "polymer" (N = 40,
+4096 chains), "copy" (device copy of known size, for counter calibration).
 """
 from __future__ import annotations
 
@@ -27,10 +32,10 @@ sys.path.insert(0, ROOT)
 
 # Peak 32-bit integer VALU rate of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz.
 PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
-# Algorithmic 32-bit VALU slot-ops per Ising attempt ("Roofline"):
-# Philox4x32-10 100 slots per 4 words (10 rounds x [2 wide multiplies at 4
-# slots + 2 three-input XORs]) = 25 per attempt; Metropolis update 20.
-OPS_PER_ATTEMPT = 45.0
+# Algorithmic 32-bit operations per Ising attempt (counted in the design doc):
+# Philox4x32-10 10 per word (10 rounds x [2 wide multiplies + 2 three-input
+# XORs] per 4 words) + Metropolis update 13.
+OPS_PER_ATTEMPT = 23.0
 
 
 def parse():
@@ -38,15 +43,22 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ising64",
+                    choices=["ising64", "batched", "serving", "polymer", "copy"])
     ap.add_argument("--sweeps", type=int, default=10000, help="sweeps per iteration (workload: 10^4)")
+    ap.add_argument("--lanes-per-chain", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched_vs_plain sub-object")
+    ap.add_argument("--batched-rounds", type=int, default=3)
+    ap.add_argument("--max-iters", type=int, default=40)
+    ap.add_argument("--requests", type=int, default=200)
     return ap.parse_args()
 
 
 def cpu_baseline(seconds: float) -> dict:
     """The oracle (single-threaded C, as it stands) on a bounded sample of the
-    same workload: 16 of the 4096 chains, L = 64, lnW = 0 thresholds, in
+    headline workload: 16 of the 4096 chains, L = 64, lnW = 0 thresholds, in
     100-sweep chunks until `seconds` have elapsed."""
     from oracle import oracle as orc
     orc.build(force=False)
@@ -61,24 +73,109 @@ def cpu_baseline(seconds: float) -> dict:
     dt = time.perf_counter() - t0
     attempts = 16 * 4096 * sweeps
     return {"value": attempts / dt, "unit": "attempts/s", "cores": 1, "kind": "oracle",
-            "sample": f"Ising L=64, 16 of the 4096 chains, {sweeps} sweeps ({attempts:.3g} attempts, "
-                      f"{dt:.1f} s, single thread)"}
+            "sample": f"Ising L=64, 16 of the 4096 chains, {sweeps} sweeps with lnW = 0 ({attempts:.3g} "
+                      f"attempts in {dt:.1f} s, single thread)"}
 
 
-def main():
-    args = parse()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
-        sys.exit(2)
+def batched_instances():
+    from paper_1312_2213_amd import muca
+    from synth import WORKLOADS, sweeps_per_iteration
+    out = []
+    for inst in WORKLOADS["potts8_batched"]["instances"]:
+        if inst["model"] == "potts":
+            cfg = muca.muca_config_default("potts", inst["L"], inst["q"], inst["chains"], inst["seed"])
+            sw = sweeps_per_iteration(inst["L"], inst["chains"], True)
+        else:
+            cfg = muca.muca_config_default("muma", inst["L"], 2, inst["chains"], inst["seed"],
+                                           beta=inst["beta"], layout=muca.MUCA_LAYOUT_BYTE)
+            sw = sweeps_per_iteration(inst["L"], inst["chains"], False)
+        out.append((cfg, sw))
+    return out
 
+
+def batched_vs_plain(rounds: int, max_iters: int | None = None) -> dict:
+    """Same instances, same iterations: one batched graph launch per round vs
+    plain launches one instance after another.  With max_iters, every
+    instance runs until flat (or the cap) and time to flat is reported."""
+    import torch
+    from paper_1312_2213_amd import muca
+    specs = batched_instances()
+    stream = torch.cuda.Stream()
+
+    def run_plain():
+        runs = [muca.Run(c, stream=stream) for c, _ in specs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ttf = []
+        iters = []
+        for (c, sw), r in zip(specs, runs):
+            n = 0
+            while True:
+                r.run_iteration(sw, stream=stream)
+                st = r.merge_update()
+                n += 1
+                if max_iters is None:
+                    if n >= rounds:
+                        break
+                elif st["flat"] or n >= max_iters:
+                    break
+            ttf.append(time.perf_counter() - t0)
+            iters.append(n)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, ttf, iters, runs
+
+    def run_batched():
+        runs = [muca.Run(c, stream=stream) for c, _ in specs]
+        batch = muca.Batch(len(runs), lanes_per_chain=4, use_graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        live = list(range(len(runs)))
+        n = [0] * len(runs)
+        ttf = [0.0] * len(runs)
+        flat = [False] * len(runs)
+        while live:
+            with torch.cuda.stream(stream):
+                batch.run_iteration([runs[k] for k in live], [specs[k][1] for k in live], stream=stream)
+            nxt = []
+            for k in live:
+                st = runs[k].merge_update()
+                n[k] += 1
+                flat[k] = bool(st["flat"])
+                done = n[k] >= rounds if max_iters is None else (st["flat"] or n[k] >= max_iters)
+                if done:
+                    ttf[k] = time.perf_counter() - t0
+                else:
+                    nxt.append(k)
+            live = nxt
+        torch.cuda.synchronize()
+        run_batched.flat = flat
+        return time.perf_counter() - t0, ttf, n, runs
+
+    tb, ttf_b, it_b, runs_b = run_batched()
+    tp, ttf_p, it_p, runs_p = run_plain()
+    same = all((a.last_hist() == b.last_hist()).all() for a, b in zip(runs_b, runs_p))
+    attempts = sum(c.n_chains * c.L * c.L * sw * k for (c, sw), k in zip(specs, it_b))
+    out = {"instances": "potts q=8 L=16,24,32,48 x 2048 chains + 4 x muma L=32 x 512 chains (beta 0.5)",
+           "sweeps_per_iteration": [sw for _, sw in specs], "iterations": it_b,
+           "batched_s": tb, "plain_s": tp, "speedup": tp / tb,
+           "batched_attempts_per_s": attempts / tb, "plain_attempts_per_s": attempts / tp,
+           "identical_histograms": bool(same)}
+    if max_iters is not None:
+        out.update({"time_to_flat_batched_s": ttf_b, "time_to_flat_plain_s": ttf_p,
+                    "flat": run_batched.flat,
+                    "mean_time_to_flat_batched_s": sum(ttf_b) / len(ttf_b),
+                    "mean_time_to_flat_plain_s": sum(ttf_p) / len(ttf_p)})
+    return out
+
+
+def bench_ising64(args):
     import torch
     from paper_1312_2213_amd import muca
 
     torch.cuda.set_device(0)
     L, C, seed, S = 64, 4096, 2, args.sweeps
-    cfg = muca.muca_config_default("ising", L, 2, C, seed, layout=muca.MUCA_LAYOUT_BIT)
+    cfg = muca.muca_config_default("ising", L, 2, C, seed, layout=muca.MUCA_LAYOUT_BIT,
+                                   lanes_per_chain=args.lanes_per_chain)
     stream = torch.cuda.current_stream()
     run = muca.Run(cfg, stream=stream)
     for _ in range(args.warmup):
@@ -103,6 +200,7 @@ def main():
     value = attempts_per_step * args.steps / dt
     kern_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
     achieved = OPS_PER_ATTEMPT * attempts_per_step / (kern_ms * 1e-3)
+    cycles = 2.4e9 * kern_ms * 1e-3 / (L * L * S)
 
     out = {
         "metric": "spin-flip attempts/s (MUCA iteration, 1 GPU)",
@@ -122,14 +220,97 @@ def main():
                    "L": L, "chains": C, "sweeps_per_iteration": S, "parallelism": "chains, 1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / PEAK_INT_OPS, "traffic": None,
-                     "kernel": "lattice_sweeps<Ising, L=64, bit>", "kernel_ms": kern_ms,
-                     "ops_per_attempt": OPS_PER_ATTEMPT},
+                     "kernel": "lattice_sweeps<Ising, L=64, bit-packed>", "kernel_ms": kern_ms,
+                     "ops_per_attempt": OPS_PER_ATTEMPT, "cycles_per_attempt_per_chain": cycles},
         "iterations": [{k: s[k] for k in ("iteration", "flatness", "lo_visited", "hi_visited")}
                        for s in stats],
     }
+    if not args.no_batched:
+        out["batched_vs_plain"] = batched_vs_plain(args.batched_rounds)
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(args.cpu_seconds)
-        out["cpu_baseline"] = cb
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    return out
+
+
+def bench_serving(args):
+    from paper_1312_2213_amd.serve import Request, Server, summarize
+    from synth import request_stream
+    reqs = [Request(id=r["id"], arrival=r["arrival"], model=r["model"], L=r["L"], q=r["q"],
+                    chains=r["chains"], seed=r["seed"], max_iters=args.max_iters)
+            for r in request_stream(args.requests, 4.0, 4)]
+    srv = Server(hbm_budget=64 << 20)
+    t0 = time.perf_counter()
+    res = srv.serve(reqs, realtime=True)
+    s = summarize(res, time.perf_counter() - t0)
+    s.update({"metric": "time-to-flat-histogram p50/p99 and aggregate attempts/s (serving, 1 GPU)",
+              "workload": f"{args.requests} Poisson requests at 4/s, seed 4; Ising L in {{16..64}} or "
+                          "Potts q in {2..10}, L in {16,32}; 256-2048 chains; flatness 0.5; "
+                          f"max {args.max_iters} iterations; HBM budget 64 MiB",
+              "rounds": srv.rounds, "peak_active": srv.peak_active})
+    return s
+
+
+def bench_polymer(args):
+    import numpy as np
+    import torch
+    from paper_1312_2213_amd import muca
+    from synth import polymer_walk
+    C, N, S = 4096, 40, 1000
+    pos = polymer_walk(N, C, 5)
+    cfg = muca.muca_config_default("polymer", 0, 2, C, 5, n_beads=N)
+    stream = torch.cuda.current_stream()
+    run = muca.Run(cfg, positions=pos, stream=stream)
+    run.run_iteration(S)
+    run.merge_update()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    kern = 0.0
+    for _ in range(args.steps):
+        e0.record(stream)
+        run.run_iteration(S)
+        e1.record(stream)
+        run.merge_update()
+        kern += e0.elapsed_time(e1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    moves = C * N * S * args.steps
+    return {"metric": "polymer displacement attempts/s (MUCA iteration, 1 GPU)", "value": moves / dt,
+            "unit": "moves/s", "kernel_moves_per_s": moves / (kern * 1e-3), "ms_per_step": dt / args.steps * 1e3,
+            "kernel_ms_per_step": kern / args.steps, "steps": args.steps,
+            "config": {"workload": "bead-spring homopolymer N=40, 4096 chains, seed 5, 1000 sweeps per "
+                                   "iteration, 2500 bins on [-200, 50)"}}
+
+
+def bench_copy():
+    """Device copy of 256 MiB (read 256 MiB, write 256 MiB), to scale HBM counters."""
+    import torch
+    n = 256 << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"workload": "copy", "bytes_read_per_copy": n, "bytes_written_per_copy": n, "copies": 3}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "ising64":
+        out = bench_ising64(args)
+    elif args.workload == "batched":
+        out = batched_vs_plain(args.batched_rounds, max_iters=args.max_iters)
+    elif args.workload == "serving":
+        out = bench_serving(args)
+    elif args.workload == "polymer":
+        out = bench_polymer(args)
+    else:
+        out = bench_copy()
     print(json.dumps(out), flush=True)
 
 

@@ -1,0 +1,200 @@
+"""Continuous-batching server for multicanonical runs.
+
+Requests (a lattice model, L, q, chains and seed) arrive over time.  A
+request is admitted as soon as its device footprint (muca_workspace_bytes)
+fits in the HBM budget and its chains fit in the chain-slot budget; its
+chain state and weights then stay resident on the device until it retires.
+Every round is ONE persistent batched launch over all admitted requests:
+each advances by a chunk of sweeps sized so that a round costs about the
+same number of site updates per chain for every request (small lattices do
+not wait behind large ones).  When a request has run the sweeps of its
+current iteration, the iteration is merged (muca_merge_update: histogram
+merge, flatness, accumulated-statistics recursion, new thresholds); the
+request retires when its histogram is flat or after max_iters iterations.
+
+Chunking only moves launch boundaries, so every request's result is
+bit-identical to running it alone.
+
+Sweeps per iteration follow the paper's M_opt(L, p) power laws (Eq. 4) for
+p = 1, divided over the request's chains (at least 10).
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import muca
+from synth.workloads import sweeps_per_iteration
+
+
+@dataclass
+class Request:
+    id: int
+    arrival: float
+    model: str
+    L: int
+    q: int
+    chains: int
+    seed: int
+    flat_threshold: float = 0.5
+    max_iters: int = 1000
+    sweeps_per_iter: int = 0
+
+    def config(self):
+        kw = {"flat_threshold": self.flat_threshold, "layout": muca.MUCA_LAYOUT_BIT if self.model == "ising"
+              else muca.MUCA_LAYOUT_AUTO}
+        return muca.muca_config_default(self.model, self.L, self.q, self.chains, self.seed, **kw)
+
+    def __post_init__(self):
+        if not self.sweeps_per_iter:
+            potts_fit = self.model == "potts" and self.q >= 5
+            self.sweeps_per_iter = sweeps_per_iteration(self.L, self.chains, potts_fit)
+
+
+@dataclass
+class Result:
+    id: int
+    arrival: float
+    admitted: float = 0.0
+    finished: float = 0.0
+    iterations: int = 0
+    flat: bool = False
+    flatness: float = 0.0
+    attempts: int = 0
+    lnw: np.ndarray | None = field(default=None, repr=False)
+    hist: np.ndarray | None = field(default=None, repr=False)
+
+    @property
+    def time_to_flat(self) -> float:
+        return self.finished - self.arrival
+
+
+class _Active:
+    def __init__(self, req: Request, run: muca.Run, footprint: int, res: Result):
+        self.req, self.run, self.footprint, self.res = req, run, footprint, res
+        self.done_in_iter = 0
+
+
+class Server:
+    def __init__(self, hbm_budget: int = 64 << 20, chain_slots: int = 1 << 16,
+                 round_site_updates: int = 1 << 16, lanes_per_chain: int = 4, use_graph: bool = True,
+                 max_active: int = 256, keep_results: bool = False, stream=None):
+        import torch
+        self.hbm_budget = hbm_budget
+        self.chain_slots = chain_slots
+        self.round_site_updates = round_site_updates
+        self.keep = keep_results
+        self.stream = stream or torch.cuda.Stream()
+        self.batch = muca.Batch(max_active, max_items=1 << 15, lanes_per_chain=lanes_per_chain,
+                                use_graph=use_graph)
+        self.max_active = max_active
+        self.rounds = 0
+        self.peak_active = 0
+
+    def _chunk(self, a: _Active) -> int:
+        per_round = max(1, self.round_site_updates // (a.req.L * a.req.L))
+        return min(per_round, a.req.sweeps_per_iter - a.done_in_iter)
+
+    def serve(self, requests: list[Request], realtime: bool = True) -> list[Result]:
+        """Runs the requests to completion; arrival times are seconds from start
+        (realtime) or only an ordering (realtime=False: all present at t = 0)."""
+        import torch
+        pending = sorted(requests, key=lambda r: (r.arrival, r.id))
+        queue: list[Request] = []
+        active: list[_Active] = []
+        results: dict[int, Result] = {}
+        used_mem = 0
+        used_chains = 0
+        t0 = time.perf_counter()
+
+        def now():
+            return time.perf_counter() - t0
+
+        while pending or queue or active:
+            t = now()
+            while pending and (not realtime or pending[0].arrival <= t):
+                queue.append(pending.pop(0))
+            # admission, first come first served
+            while queue and len(active) < self.max_active:
+                req = queue[0]
+                cfg = req.config()
+                fp = muca.muca_workspace_bytes(cfg)
+                if active and (used_mem + fp > self.hbm_budget or used_chains + req.chains > self.chain_slots):
+                    break
+                queue.pop(0)
+                with torch.cuda.stream(self.stream):
+                    run = muca.Run(cfg, stream=self.stream)
+                res = Result(req.id, req.arrival if realtime else 0.0, admitted=now())
+                results[req.id] = res
+                active.append(_Active(req, run, fp, res))
+                used_mem += fp
+                used_chains += req.chains
+            self.peak_active = max(self.peak_active, len(active))
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, min(0.01, pending[0].arrival - now())))
+                continue
+            chunks = [self._chunk(a) for a in active]
+            with torch.cuda.stream(self.stream):
+                self.batch.run_iteration([a.run for a in active], chunks, stream=self.stream)
+            self.rounds += 1
+            still = []
+            for a, ch in zip(active, chunks):
+                a.done_in_iter += ch
+                a.res.attempts += ch * a.req.chains * a.req.L * a.req.L
+                if a.done_in_iter < a.req.sweeps_per_iter:
+                    still.append(a)
+                    continue
+                st = a.run.merge_update()
+                a.done_in_iter = 0
+                a.res.iterations += 1
+                a.res.flatness = st["flatness"]
+                if st["flat"] or a.res.iterations >= a.req.max_iters:
+                    a.res.flat = bool(st["flat"])
+                    a.res.finished = now()
+                    if self.keep:
+                        a.res.lnw = a.run.lnw()
+                        a.res.hist = a.run.last_hist()
+                    a.run.free()
+                    used_mem -= a.footprint
+                    used_chains -= a.req.chains
+                else:
+                    still.append(a)
+            active = still
+        torch.cuda.synchronize()
+        return [results[r.id] for r in sorted(requests, key=lambda r: r.id)]
+
+
+def run_alone(req: Request, stream=None) -> Result:
+    """Plain per-request loop of single launches (one launch per iteration)."""
+    import torch
+    t0 = time.perf_counter()
+    run = muca.Run(req.config(), stream=stream)
+    res = Result(req.id, 0.0)
+    while True:
+        run.run_iteration(req.sweeps_per_iter, stream=stream)
+        st = run.merge_update()
+        res.iterations += 1
+        res.attempts += req.sweeps_per_iter * req.chains * req.L * req.L
+        res.flatness = st["flatness"]
+        if st["flat"] or res.iterations >= req.max_iters:
+            res.flat = bool(st["flat"])
+            break
+    res.lnw = run.lnw()
+    res.hist = run.last_hist()
+    torch.cuda.synchronize()
+    res.finished = time.perf_counter() - t0
+    run.free()
+    return res
+
+
+def summarize(results: list[Result], makespan: float) -> dict:
+    ttf = np.array([r.time_to_flat for r in results])
+    attempts = sum(r.attempts for r in results)
+    return {"requests": len(results), "flat": int(sum(r.flat for r in results)),
+            "p50_time_to_flat_s": float(np.percentile(ttf, 50)),
+            "p99_time_to_flat_s": float(np.percentile(ttf, 99)),
+            "mean_time_to_flat_s": float(ttf.mean()), "makespan_s": makespan,
+            "attempts": attempts, "attempts_per_s": attempts / makespan if makespan > 0 else 0.0}
