@@ -11,6 +11,9 @@ import ctypes
 import os
 
 import numpy as np
+# torch first: its HIP runtime (libamdhip64.so.7) is then the one libmuca.so
+# binds to, so the process never holds two HIP/HSA runtimes.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmuca.so")

@@ -92,6 +92,7 @@ class Server:
         self.max_active = max_active
         self.rounds = 0
         self.peak_active = 0
+        self.peak_mem = 0
 
     def _chunk(self, a: _Active) -> int:
         per_round = max(1, self.round_site_updates // (a.req.L * a.req.L))
@@ -132,6 +133,7 @@ class Server:
                 used_mem += fp
                 used_chains += req.chains
             self.peak_active = max(self.peak_active, len(active))
+            self.peak_mem = max(self.peak_mem, used_mem)
             if not active:
                 if pending:
                     time.sleep(max(0.0, min(0.01, pending[0].arrival - now())))
