@@ -76,9 +76,11 @@ struct RowRng {
             if (kCalls % LPC)
                 call = call < (uint32_t)kCalls ? call : (uint32_t)kCalls - 1u; // surplus lanes: any valid call
             const Words4 r = philox4x32_10(chain, g, (uint32_t)(y * kCalls) + call, kTagSweep, k0, k1);
+            // acceptance words are clamped to 2^32 - 2 once here, so that
+            // "accept iff T == 2^32 - 1 or r < T" is the single compare r < T
 #pragma unroll
             for (int t = 0; t < 4; ++t)
-                w[4 * m + t] = r.w[t];
+                w[4 * m + t] = (WPS == 1 || (t & 1)) ? min(r.w[t], 0xFFFFFFFEu) : r.w[t];
         }
     }
 
@@ -119,44 +121,107 @@ struct Row1 {
     static constexpr int W = (L + 31) / 32;
 };
 
-template <int MODEL, int L, int LPC, int WI, int K>
-__device__ __forceinline__ void ising_bit(uint32_t &F, uint32_t &f, int32_t &bidx, const RowRng<L, LPC, 1> &rng,
-                                          uint32_t S, uint32_t s0, uint32_t s1, uint32_t ML, uint32_t MU,
-                                          uint32_t MD, const uint32_t *__restrict__ T)
+// Four times the number of misaligned neighbours of site K of word WI,
+// given the flip f of the previous site of the word (K > 0).  For a row of
+// one word, the last site's right neighbour is site 0 of the same word, read
+// from its current value.
+// f4 is the previous site's flip times 4 (0 or 4).
+template <int L, int WI, int K>
+__device__ __forceinline__ int32_t misaligned4(uint32_t S, uint32_t F, uint32_t s0, uint32_t s1, uint32_t ML,
+                                               uint32_t MU, uint32_t MD, uint32_t f4)
 {
-    constexpr int X = 32 * WI + K; // column of the site
-    constexpr int NC = Cols<MODEL>::value;
-    const uint32_t r = min(rng.template get<X, 0>(), 0xFFFFFFFEu); // accept iff r < T (T = ~0: always)
-    uint32_t ml = (ML >> K) & 1u;
+    constexpr int X = 32 * WI + K;
+    uint32_t ml4 = ((ML >> K) & 1u) << 2;
     if constexpr (K > 0)
-        ml ^= f; // the previous site of this word may have flipped
-    int32_t nmis;
+        ml4 ^= f4;
     if constexpr (Row1<L>::W == 1 && X == L - 1 && L > 1) {
-        // right neighbour is site 0 of this word: read its current value
-        const uint32_t s = (S >> K) & 1u;
-        const uint32_t mr = s ^ ((S ^ F) & 1u);
-        nmis = (int32_t)(mr + ((MU >> K) & 1u) + ((MD >> K) & 1u) + ml);
+        const uint32_t mr = ((S >> K) & 1u) ^ ((S ^ F) & 1u);
+        return (int32_t)(((mr + ((MU >> K) & 1u) + ((MD >> K) & 1u)) << 2) + ml4);
     } else {
-        nmis = (int32_t)((((s1 >> K) & 1u) << 1) + ((s0 >> K) & 1u) + ml);
+        return (int32_t)((((((s1 >> K) & 1u) << 1) + ((s0 >> K) & 1u)) << 2) + ml4);
     }
-    int32_t col, dstep;
-    if constexpr (MODEL == kIsing) {
-        col = 4 - nmis;          // aligned neighbours
-        dstep = (2 - nmis) * NC; // dE = 4 (n_al - 2): one bin per 4
-    } else {
-        const int32_t plus = (int32_t)((S >> K) & 1u);
-        col = 2 * (4 - nmis) + plus;
-        dstep = plus ? -NC : NC; // M changes by -2 s_i: one bin per 2
-    }
-    const uint32_t t = T[bidx + col];
-    f = r < t ? 1u : 0u;
-    F |= f << K;
-    bidx += (int32_t)f * dstep;
 }
 
-template <int MODEL, int L, int LPC, int WI, int... K>
+// Threshold address of a site with nmis4 = 4 x misaligned neighbours,
+// relative to the current bin's row origin `rowb` (bytes):
+//   Ising: column 4 - nmis (aligned neighbours); origin = column 4.
+//   MUMA:  column 2 (4 - nmis) + plus;         origin = column 8.
+template <int MODEL>
+__device__ __forceinline__ int32_t col_addr(int32_t rowb, int32_t nmis4, uint32_t plus)
+{
+    if constexpr (MODEL == kIsing)
+        return rowb - nmis4;
+    else
+        return rowb + (int32_t)(plus << 2) - 2 * nmis4;
+}
+
+template <int MODEL>
+constexpr int32_t row_origin() { return MODEL == kIsing ? 4 : 8; }
+
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+
+// Threshold at `addr`: an absolute LDS byte address when the table is staged
+// in LDS, else a byte offset from the global table.
+template <bool TLDS>
+__device__ __forceinline__ uint32_t load_t(const uint32_t *__restrict__ T, int32_t addr)
+{
+    if constexpr (TLDS)
+        return *(lds_u32 *)(uintptr_t)(uint32_t)addr;
+    else
+        return *(const uint32_t *)((const char *)T + addr);
+}
+
+// Byte shift of the row origin when a site with nmis4 = 4 x misaligned
+// neighbours flips: Ising dE = 4 (n_al - 2), one bin per 4; MUMA M changes by
+// -2 s_i, one bin per 2.
+template <int MODEL>
+__device__ __forceinline__ int32_t bin_step(int32_t nmis4, uint32_t plus)
+{
+    constexpr int NC = Cols<MODEL>::value;
+    if constexpr (MODEL == kIsing)
+        return nmis4 * (-NC) + 8 * NC;
+    else
+        return plus ? -4 * NC : 4 * NC;
+}
+
+// Site K of word WI.  `addr` (threshold address) and `dstep` (row-origin
+// shift on acceptance) of this site were selected when the previous site was
+// decided.  While this site's threshold read is in flight, both candidates
+// for the next site (this site rejected / accepted) are computed from the bit
+// planes, so after the compare a single select yields the next address: the
+// loop-carried chain is LDS read -> compare -> select.
+template <int MODEL, int L, int LPC, bool TLDS, int WI, int K>
+__device__ __forceinline__ void ising_site(uint32_t &F, int32_t &rowb, int32_t &addr, int32_t &dstep,
+                                           const RowRng<L, LPC, 1> &rng, uint32_t S, uint32_t s0, uint32_t s1,
+                                           uint32_t ML, uint32_t MU, uint32_t MD, const uint32_t *__restrict__ T)
+{
+    constexpr int X = 32 * WI + K;
+    constexpr int NB = (L - 32 * WI) < 32 ? (L - 32 * WI) : 32;
+    const uint32_t t = load_t<TLDS>(T, addr);
+    const uint32_t r = rng.template get<X, 0>(); // clamped: accept iff r < T
+    const int32_t rowb_acc = rowb + dstep;
+    int32_t addr0 = 0, addr1 = 0, dstep0 = 0, dstep1 = 0;
+    if constexpr (K + 1 < NB) {
+        const uint32_t plus1 = (S >> (K + 1)) & 1u;
+        const int32_t n0 = misaligned4<L, WI, K + 1>(S, F, s0, s1, ML, MU, MD, 0u);
+        const int32_t n1 = misaligned4<L, WI, K + 1>(S, F, s0, s1, ML, MU, MD, 4u);
+        addr0 = col_addr<MODEL>(rowb, n0, plus1);
+        addr1 = col_addr<MODEL>(rowb_acc, n1, plus1);
+        dstep0 = bin_step<MODEL>(n0, plus1);
+        dstep1 = bin_step<MODEL>(n1, plus1);
+    }
+    const bool acc = r < t;
+    F |= (acc ? 1u : 0u) << K;
+    rowb = acc ? rowb_acc : rowb;
+    if constexpr (K + 1 < NB) {
+        addr = acc ? addr1 : addr0;
+        dstep = acc ? dstep1 : dstep0;
+    }
+}
+
+template <int MODEL, int L, int LPC, bool TLDS, int WI, int... K>
 __device__ __forceinline__ void ising_word(const uint32_t (&up)[Row1<L>::W], uint32_t (&cur)[Row1<L>::W],
-                                           const uint32_t (&dn)[Row1<L>::W], int32_t &bidx,
+                                           const uint32_t (&dn)[Row1<L>::W], int32_t &rowb,
                                            const RowRng<L, LPC, 1> &rng, const uint32_t *__restrict__ T,
                                            std::integer_sequence<int, K...>)
 {
@@ -170,21 +235,24 @@ __device__ __forceinline__ void ising_word(const uint32_t (&up)[Row1<L>::W], uin
     const uint32_t MR = S ^ Rn, MU = S ^ up[WI], MD = S ^ dn[WI], ML = S ^ Ln;
     const uint32_t s0 = MR ^ MU ^ MD;
     const uint32_t s1 = (MR & MU) | (MR & MD) | (MU & MD);
-    uint32_t F = 0u, f = 0u;
-    (ising_bit<MODEL, L, LPC, WI, K>(F, f, bidx, rng, S, s0, s1, ML, MU, MD, T), ...);
+    uint32_t F = 0u;
+    const int32_t n = misaligned4<L, WI, 0>(S, 0u, s0, s1, ML, MU, MD, 0u);
+    int32_t addr = col_addr<MODEL>(rowb, n, S & 1u);
+    int32_t dstep = bin_step<MODEL>(n, S & 1u);
+    (ising_site<MODEL, L, LPC, TLDS, WI, K>(F, rowb, addr, dstep, rng, S, s0, s1, ML, MU, MD, T), ...);
     cur[WI] = S ^ F;
 }
 
-template <int MODEL, int L, int LPC, int... WI>
+template <int MODEL, int L, int LPC, bool TLDS, int... WI>
 __device__ __forceinline__ void ising_row(const uint32_t (&up)[Row1<L>::W], uint32_t (&cur)[Row1<L>::W],
-                                          const uint32_t (&dn)[Row1<L>::W], int32_t &bidx,
+                                          const uint32_t (&dn)[Row1<L>::W], int32_t &rowb,
                                           const uint32_t *__restrict__ T, uint32_t chain, uint32_t g, int y,
                                           uint32_t j, uint32_t k0, uint32_t k1, std::integer_sequence<int, WI...>)
 {
     RowRng<L, LPC, 1> rng;
     rng.fill(chain, g, y, j, k0, k1);
-    (ising_word<MODEL, L, LPC, WI>(up, cur, dn, bidx, rng, T,
-                                   std::make_integer_sequence<int, ((L - 32 * WI) < 32 ? (L - 32 * WI) : 32)>{}),
+    (ising_word<MODEL, L, LPC, TLDS, WI>(up, cur, dn, rowb, rng, T,
+                                         std::make_integer_sequence<int, ((L - 32 * WI) < 32 ? (L - 32 * WI) : 32)>{}),
      ...);
 }
 
@@ -239,7 +307,7 @@ __device__ __forceinline__ void potts_site(const uint32_t (&up)[W], uint32_t (&c
                                            const uint32_t *__restrict__ T, uint32_t q)
 {
     const uint32_t wp = rng.template get<X, 0>();
-    const uint32_t r = min(rng.template get<X, 1>(), 0xFFFFFFFEu);
+    const uint32_t r = rng.template get<X, 1>(); // clamped in RowRng::fill
     const uint32_t old = colour<L>(cur, X);
     uint32_t nw = old + 1u + __umulhi(wp, q - 1u);
     nw = nw >= q ? nw - q : nw;
@@ -280,16 +348,17 @@ template <int MODEL, int L, int LAYOUT, bool TLDS, int LPC>
 __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, uint32_t *smem)
 {
     constexpr int NC = Cols<MODEL>::value;
-    uint32_t *lhist = smem;
+    // LDS: [threshold table (staged) | histogram]; the table starts at LDS
+    // address 0 so a threshold address is a single byte offset
+    uint32_t *lhist = TLDS ? smem + a.n_bins * NC : smem;
     const int tid = threadIdx.x;
     for (int i = tid; i < a.n_bins; i += blockDim.x)
         lhist[i] = 0u;
     const uint32_t *T = a.thresholds;
     if constexpr (TLDS) {
-        uint32_t *ltab = smem + a.n_bins;
         for (int i = tid; i < a.n_bins * NC; i += blockDim.x)
-            ltab[i] = a.thresholds[i];
-        T = ltab;
+            smem[i] = a.thresholds[i];
+        T = smem;
     }
     __syncthreads();
 
@@ -342,12 +411,17 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
         load_row<L, LAYOUT>(base, stride, 0, cur);
         load_row<L, LAYOUT>(base, stride, 1 % L, dn);
         load_row<L, LAYOUT>(base, stride, 2 % L, nx);
-        int32_t bidx = b * NC; // row offset of the current bin in the threshold table
+        // the current bin's row origin in the threshold table: an absolute LDS
+        // byte address when the table is staged, else a byte offset
+        int32_t tbase = 0;
+        if constexpr (TLDS)
+            tbase = (int32_t)(uint32_t)(uintptr_t)(lds_u32 *)smem;
+        int32_t rowb = tbase + 4 * (b * NC + row_origin<MODEL>());
         for (int s = 0; s < a.n_sweeps; ++s) {
             const uint32_t g = a.g0 + (uint32_t)s;
             for (int y = 0; y < L; ++y) {
-                ising_row<MODEL, L, LPC>(up, cur, dn, bidx, T, chain, g, y, j, a.k0, a.k1,
-                                         std::make_integer_sequence<int, W>{});
+                ising_row<MODEL, L, LPC, TLDS>(up, cur, dn, rowb, T, chain, g, y, j, a.k0, a.k1,
+                                               std::make_integer_sequence<int, W>{});
                 if (leader)
                     store_row<L, LAYOUT>(base, stride, y, cur);
 #pragma unroll
@@ -359,9 +433,9 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
                 load_row<L, LAYOUT>(base, stride, (y + 3) % L, nx);
             }
             if (counts)
-                atomicAdd(&lhist[bidx / NC], 1u);
+                atomicAdd(&lhist[(((rowb - tbase) >> 2) - row_origin<MODEL>()) / NC], 1u);
         }
-        b = bidx / NC;
+        b = (((rowb - tbase) >> 2) - row_origin<MODEL>()) / NC;
     }
     if (leader)
         a.bins[c] = b;
