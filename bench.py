@@ -47,6 +47,7 @@ def parse():
                     choices=["ising64", "batched", "serving", "polymer", "copy"])
     ap.add_argument("--sweeps", type=int, default=10000, help="sweeps per iteration (workload: 10^4)")
     ap.add_argument("--lanes-per-chain", type=int, default=0)
+    ap.add_argument("--batch-lanes-per-chain", type=int, default=0, help="batched runs: 4, 16 or 0 (per run)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched_vs_plain sub-object")
@@ -93,7 +94,7 @@ def batched_instances():
     return out
 
 
-def batched_vs_plain(rounds: int, max_iters: int | None = None) -> dict:
+def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int = 0) -> dict:
     """Same instances, same iterations: one batched graph launch per round vs
     plain launches one instance after another.  With max_iters, every
     instance runs until flat (or the cap) and time to flat is reported."""
@@ -126,7 +127,7 @@ def batched_vs_plain(rounds: int, max_iters: int | None = None) -> dict:
 
     def run_batched():
         runs = [muca.Run(c, stream=stream) for c, _ in specs]
-        batch = muca.Batch(len(runs), lanes_per_chain=4, use_graph=True)
+        batch = muca.Batch(len(runs), lanes_per_chain=batch_lpc, use_graph=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         live = list(range(len(runs)))
@@ -226,7 +227,7 @@ def bench_ising64(args):
                        for s in stats],
     }
     if not args.no_batched:
-        out["batched_vs_plain"] = batched_vs_plain(args.batched_rounds)
+        out["batched_vs_plain"] = batched_vs_plain(args.batched_rounds, batch_lpc=args.batch_lanes_per_chain)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     return out
@@ -304,7 +305,7 @@ def main():
     if args.workload == "ising64":
         out = bench_ising64(args)
     elif args.workload == "batched":
-        out = batched_vs_plain(args.batched_rounds, max_iters=args.max_iters)
+        out = batched_vs_plain(args.batched_rounds, max_iters=args.max_iters, batch_lpc=args.batch_lanes_per_chain)
     elif args.workload == "serving":
         out = bench_serving(args)
     elif args.workload == "polymer":

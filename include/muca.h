@@ -150,7 +150,10 @@ int muca_reweight(const muca_run *run, const double *betas, int32_t n, double *o
  * bit-identical to plain launches.
  *   muca_batch_workspace_bytes: device bytes for up to max_runs runs and
  *     max_items work items.
- *   muca_batch_create: lanes_per_chain 4 or 16; use_graph != 0 captures
+ *   muca_batch_create: lanes_per_chain 4 or 16 for every run, or 0 to
+ *     choose per launch: runs start at 4 and, longest per-chain work first,
+ *     move to 16 while all lanes fit one 256-thread workgroup per compute
+ *     unit and the items fit max_items.  use_graph != 0 captures
  *     [descriptor upload, queue reset, persistent kernel] in a hipGraph once
  *     and relaunches it (requires a non-null stream).  d_ws is caller-owned
  *     (256-byte aligned); the handle owns a small pinned host buffer.

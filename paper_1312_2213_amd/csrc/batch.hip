@@ -145,8 +145,8 @@ extern "C" int muca_batch_create(int32_t max_runs, int32_t max_items, int32_t la
     if (ws_bytes < need)
         return muca_fail(MUCA_E_NOMEM, "batch workspace of %llu bytes, need %llu", (unsigned long long)ws_bytes,
                          (unsigned long long)need);
-    if (lanes_per_chain != 4 && lanes_per_chain != 16)
-        return muca_fail(MUCA_E_ARG, "batched launches use 4 or 16 lanes per chain");
+    if (lanes_per_chain != 0 && lanes_per_chain != 4 && lanes_per_chain != 16)
+        return muca_fail(MUCA_E_ARG, "batched launches use 4 or 16 lanes per chain (0: chosen per run)");
     muca_batch *b = new muca_batch();
     b->max_runs = max_runs;
     b->max_items = max_items;
@@ -241,7 +241,38 @@ extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, in
     if (n > b->max_runs)
         return muca_fail(MUCA_E_ARG, "%d runs exceed the batch capacity %d", n, b->max_runs);
     hipStream_t s = (hipStream_t)stream;
-    const int cpi = 256 / b->lpc; // chains per item
+    // lanes per chain of each run.  Automatic choice: every run starts at 4;
+    // runs are raised to 16 in order of decreasing per-chain work (the
+    // critical path of the launch) while all lanes still fit one resident
+    // 256-thread workgroup per CU and the item list its capacity.
+    std::vector<int> lpc(n, b->lpc ? b->lpc : 4);
+    if (b->lpc == 0) {
+        std::vector<int> order(n);
+        long lanes = 0, n_items = 0;
+        for (int i = 0; i < n; ++i) {
+            order[i] = i;
+            if (runs[i]) {
+                lanes += (long)runs[i]->g.c_pad * 4;
+                n_items += runs[i]->g.c_pad / 64;
+            }
+        }
+        auto work = [&](int i) {
+            return (runs[i]->g.model == kPotts ? 2.0 : 1.0) * (double)runs[i]->g.n_sites * (double)sweeps[i];
+        };
+        for (int i = 0; i < n; ++i)
+            if (!runs[i])
+                return muca_fail(MUCA_E_STATE, "run %d is null", i);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+        const long cap = (long)b->n_cus * 256;
+        for (int i : order) {
+            const long extra = (long)runs[i]->g.c_pad * 12, extra_items = runs[i]->g.c_pad / 16 - runs[i]->g.c_pad / 64;
+            if (lanes + extra > cap || n_items + extra_items > b->max_items)
+                break;
+            lanes += extra;
+            n_items += extra_items;
+            lpc[i] = 16;
+        }
+    }
     struct Item {
         double cost;
         int inst, c_first;
@@ -259,15 +290,15 @@ extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, in
         const int kind = kind_of(r), li = l_index(r->g.L);
         if (kind < 0 || li < 0)
             return muca_fail(MUCA_E_ARG, "run %d (model %d, L %d) has no batched variant", i, r->g.model, r->g.L);
-        if (sweeps[i] < 1 || sweeps[i] > (int64_t)(0xFFFFFFFFll / cpi) - 1)
+        const int cpi = 256 / lpc[i]; // chains per item
+        if (sweeps[i] < 1 || sweeps[i] > (int64_t)INT32_MAX)
             return muca_fail(MUCA_E_ARG, "run %d: sweeps %lld out of range", i, (long long)sweeps[i]);
         for (int k = 0; k < i; ++k)
             if (runs[k] == r)
                 return muca_fail(MUCA_E_ARG, "run %d appears twice", i);
-        const size_t hist = (size_t)r->g.n_bins * 4u;
-        const size_t tab = (size_t)r->g.n_bins * r->g.n_cols * 4u;
-        const bool tlds = r->g.table_in_lds && hist + tab <= lds_budget;
-        lds = std::max(lds, hist + (tlds ? tab : 0));
+        const size_t hist = (size_t)lds_hist_words(r->g.n_bins) * 4u;
+        const bool tlds = r->g.table_in_lds && r->g.lds_bytes <= lds_budget;
+        lds = std::max(lds, tlds ? r->g.lds_bytes : hist);
         BatchDesc &d = desc[i];
         std::memset(&d, 0, sizeof d);
         d.a.words = r->d_words;
@@ -285,7 +316,7 @@ extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, in
         d.a.record = 1;
         d.a.table_in_lds = tlds ? 1 : 0;
         d.a.chain0 = 0;
-        d.variant = variant_index(kind, li, tlds ? 1 : 0, b->lpc == 16 ? 1 : 0);
+        d.variant = variant_index(kind, li, tlds ? 1 : 0, lpc[i] == 16 ? 1 : 0);
         const double per_site = r->g.model == kPotts ? 2.0 : 1.0;
         const double cost = per_site * (double)r->g.n_sites * (double)sweeps[i];
         for (int c0 = 0; c0 < r->g.c_pad; c0 += cpi)

@@ -301,7 +301,7 @@ __device__ __forceinline__ void store_row(uint32_t *base, size_t stride, int y, 
 
 // One q-state Potts site update: proposal among the q-1 other colours,
 // dE = (neighbours equal to old) - (neighbours equal to new) unsatisfied bonds.
-template <int L, int LPC, int W, int X>
+template <int L, int LPC, bool TLDS, int W, int X>
 __device__ __forceinline__ void potts_site(const uint32_t (&up)[W], uint32_t (&cur)[W],
                                            const uint32_t (&dn)[W], int32_t &b, const RowRng<L, LPC, 2> &rng,
                                            const uint32_t *__restrict__ T, uint32_t q)
@@ -318,13 +318,17 @@ __device__ __forceinline__ void potts_site(const uint32_t (&up)[W], uint32_t (&c
     const int32_t n_old = (cl == old) + (cr == old) + (cu == old) + (cd == old);
     const int32_t n_new = (cl == nw) + (cr == nw) + (cu == nw) + (cd == nw);
     const int32_t dE = n_old - n_new;
-    const uint32_t t = T[b * 9 + dE + 4];
+    uint32_t t;
+    if constexpr (TLDS) // 8 staged columns: dE = -4..-1, 1..4; dE = 0 always accepts
+        t = dE == 0 ? 0xFFFFFFFFu : T[b * 8 + dE + 4 - (dE > 0 ? 1 : 0)];
+    else
+        t = T[b * 9 + dE + 4];
     const bool acc = r < t;
     cur[X / 4] ^= acc ? ((old ^ nw) << ((X % 4) * 8)) : 0u;
     b += acc ? dE : 0;
 }
 
-template <int L, int LPC, int W, int... X>
+template <int L, int LPC, bool TLDS, int W, int... X>
 __device__ __forceinline__ void potts_row(const uint32_t (&up)[W], uint32_t (&cur)[W],
                                           const uint32_t (&dn)[W], int32_t &b,
                                           const uint32_t *__restrict__ T, uint32_t chain,
@@ -333,7 +337,7 @@ __device__ __forceinline__ void potts_row(const uint32_t (&up)[W], uint32_t (&cu
 {
     RowRng<L, LPC, 2> rng;
     rng.fill(chain, g, y, j, k0, k1);
-    (potts_site<L, LPC, W, X>(up, cur, dn, b, rng, T, q), ...);
+    (potts_site<L, LPC, TLDS, W, X>(up, cur, dn, b, rng, T, q), ...);
 }
 
 // ---------------------------------------------------------------------------
@@ -344,20 +348,43 @@ __device__ __forceinline__ void potts_row(const uint32_t (&up)[W], uint32_t (&cu
 // Used by the plain kernel (one launch per instance) and by the persistent
 // batched kernel (one block per work item).
 // ---------------------------------------------------------------------------
+// Adds the block's packed LDS counters to the global histogram and clears
+// them.  Called by every thread of the block between two barriers.
+__device__ __forceinline__ void flush_hist(uint32_t *lhist, int hw, unsigned long long *hist)
+{
+    for (int i = threadIdx.x; i < hw; i += blockDim.x) {
+        const uint32_t v = lhist[i];
+        if (v) {
+            lhist[i] = 0u;
+            if (v & 0xFFFFu)
+                atomicAdd(&hist[2 * i], (unsigned long long)(v & 0xFFFFu));
+            if (v >> 16)
+                atomicAdd(&hist[2 * i + 1], (unsigned long long)(v >> 16));
+        }
+    }
+}
+
 template <int MODEL, int L, int LAYOUT, bool TLDS, int LPC>
 __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, uint32_t *smem)
 {
     constexpr int NC = Cols<MODEL>::value;
-    // LDS: [threshold table (staged) | histogram]; the table starts at LDS
-    // address 0 so a threshold address is a single byte offset
-    uint32_t *lhist = TLDS ? smem + a.n_bins * NC : smem;
+    // LDS: [threshold table (staged) | packed 16-bit histogram]
+    constexpr int NCL = MODEL == kPotts ? 8 : NC;
+    uint32_t *lhist = TLDS ? smem + a.n_bins * NCL : smem;
     const int tid = threadIdx.x;
-    for (int i = tid; i < a.n_bins; i += blockDim.x)
+    const int hw = lds_hist_words(a.n_bins);
+    for (int i = tid; i < hw; i += blockDim.x)
         lhist[i] = 0u;
     const uint32_t *T = a.thresholds;
     if constexpr (TLDS) {
-        for (int i = tid; i < a.n_bins * NC; i += blockDim.x)
-            smem[i] = a.thresholds[i];
+        for (int i = tid; i < a.n_bins * NCL; i += blockDim.x) {
+            int src = i;
+            if constexpr (MODEL == kPotts) { // skip the dE = 0 column
+                const int bb = i >> 3, cc = i & 7;
+                src = bb * 9 + cc + (cc >= 4 ? 1 : 0);
+            }
+            smem[i] = a.thresholds[src];
+        }
         T = smem;
     }
     __syncthreads();
@@ -370,6 +397,9 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
     const uint32_t chain = (uint32_t)(a.chain0 + c);
     const bool counts = a.record && c < a.n_chains && leader;
     int32_t b = a.bins[c];
+    // sweeps between two flushes of the 16-bit LDS counters
+    const int flush_every = kMaxBlockCount / (int)(blockDim.x / LPC);
+    int until_flush = flush_every;
 
     if constexpr (MODEL == kPotts) {
         constexpr int W = Geom<L, LAYOUT>::kWpr;
@@ -385,7 +415,7 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
         for (int s = 0; s < a.n_sweeps; ++s) {
             const uint32_t g = a.g0 + (uint32_t)s;
             for (int y = 0; y < L; ++y) {
-                potts_row<L, LPC, W>(up, cur, dn, b, T, chain, g, y, j, a.k0, a.k1, q,
+                potts_row<L, LPC, TLDS, W>(up, cur, dn, b, T, chain, g, y, j, a.k0, a.k1, q,
                                      std::make_integer_sequence<int, L>{});
                 const int yn = (y + 3) % L;
                 if (leader) {
@@ -402,7 +432,13 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
                 }
             }
             if (counts)
-                atomicAdd(&lhist[b], 1u);
+                atomicAdd(&lhist[b >> 1], 1u << ((b & 1) << 4));
+            if (--until_flush == 0 && s + 1 < a.n_sweeps) {
+                until_flush = flush_every;
+                __syncthreads();
+                flush_hist(lhist, hw, a.hist);
+                __syncthreads();
+            }
         }
     } else {
         constexpr int W = Row1<L>::W;
@@ -432,19 +468,23 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
                 }
                 load_row<L, LAYOUT>(base, stride, (y + 3) % L, nx);
             }
-            if (counts)
-                atomicAdd(&lhist[(((rowb - tbase) >> 2) - row_origin<MODEL>()) / NC], 1u);
+            if (counts) {
+                const int32_t bb = (((rowb - tbase) >> 2) - row_origin<MODEL>()) / NC;
+                atomicAdd(&lhist[bb >> 1], 1u << ((bb & 1) << 4));
+            }
+            if (--until_flush == 0 && s + 1 < a.n_sweeps) {
+                until_flush = flush_every;
+                __syncthreads();
+                flush_hist(lhist, hw, a.hist);
+                __syncthreads();
+            }
         }
         b = (((rowb - tbase) >> 2) - row_origin<MODEL>()) / NC;
     }
     if (leader)
         a.bins[c] = b;
     __syncthreads();
-    for (int i = tid; i < a.n_bins; i += blockDim.x) {
-        const uint32_t v = lhist[i];
-        if (v)
-            atomicAdd(&a.hist[i], (unsigned long long)v);
-    }
+    flush_hist(lhist, hw, a.hist);
 }
 
 template <int MODEL, int L, int LAYOUT, bool TLDS, int LPC>
@@ -466,9 +506,9 @@ static hipError_t launch_variant(int threads, const LatticeArgs &a, hipStream_t 
     if (threads < 64 || threads > 256 || lanes % threads)
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)(lanes / threads)), block(threads);
-    size_t lds = (size_t)a.n_bins * 4u;
+    size_t lds = (size_t)lds_hist_words(a.n_bins) * 4u;
     if (a.table_in_lds) {
-        lds += (size_t)a.n_bins * NC * 4u;
+        lds += (size_t)a.n_bins * lds_table_cols(MODEL) * 4u;
         auto k = lattice_sweeps<MODEL, L, LAYOUT, true, LPC>;
         if (lds > 65536u) {
             hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -59,6 +59,15 @@ struct PolymerConsts {
 
 hipError_t launch_polymer_sweeps(const PolymerArgs &a, const PolymerConsts &k, hipStream_t s);
 
+// LDS staging of one block: the threshold table (Potts keeps 8 of its 9
+// columns: the dE = 0 column always accepts) and a histogram of 16-bit
+// counters packed two per word.  A block adds its counters to the global
+// histogram every kMaxBlockCount / (chains per block) sweeps, so no counter
+// can carry into its neighbour.
+__host__ __device__ inline int lds_table_cols(int model) { return model == kIsing ? 5 : (model == kPotts ? 8 : 10); }
+__host__ __device__ inline int lds_hist_words(int n_bins) { return (n_bins + 1) / 2; }
+constexpr int kMaxBlockCount = 65535; // chains per block x sweeps per launch
+
 // Number of 32-bit words per lattice row.
 __host__ __device__ inline int words_per_row(int L, int layout) { return layout == kLayoutBit ? (L + 31) / 32 : (L + 3) / 4; }
 

@@ -121,13 +121,17 @@ int muca_geometry(const muca_config *c, Geometry *g)
     while (((long)g->c_pad * lpc) % cpb)
         cpb /= 2;
     g->cpb = cpb;
-    const size_t hist_lds = (size_t)g->n_bins * 4u;
+    // LDS of one block: the packed 16-bit histogram, plus the staged table
+    // (Potts stages 8 of its 9 columns)
+    const size_t hist_lds = (size_t)lds_hist_words(g->n_bins) * 4u;
+    const size_t stage_lds = (size_t)g->n_bins * lds_table_cols(g->model) * 4u;
     const size_t tab_lds = (size_t)g->n_bins * g->n_cols * 4u;
-    if (c->table_in_lds == 1 && hist_lds + tab_lds > 160u * 1024u)
-        return muca_fail(MUCA_E_ARG, "threshold table of %zu bytes does not fit in LDS", tab_lds);
+    g->lds_bytes = hist_lds + stage_lds;
+    if (c->table_in_lds == 1 && g->lds_bytes > 160u * 1024u)
+        return muca_fail(MUCA_E_ARG, "threshold table of %zu bytes does not fit in LDS", stage_lds);
     if (hist_lds > 64u * 1024u)
         return muca_fail(MUCA_E_ARG, "%d bins exceed the LDS histogram", g->n_bins);
-    g->table_in_lds = c->table_in_lds == 1 || (c->table_in_lds < 0 && hist_lds + tab_lds <= 128u * 1024u);
+    g->table_in_lds = c->table_in_lds == 1 || (c->table_in_lds < 0 && g->lds_bytes <= 160u * 1024u);
     // workspace carve
     size_t off = 0;
     g->off_words = off;
@@ -438,7 +442,7 @@ extern "C" int muca_init(const muca_config *c, void *d_ws, uint64_t ws_bytes, co
         int dev = 0, lim = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
-            const size_t need = (size_t)g.n_bins * 4u * (1u + (size_t)g.n_cols);
+            const size_t need = g.lds_bytes;
             if (need > (size_t)lim) {
                 if (c->table_in_lds == 1)
                     return muca_fail(MUCA_E_ARG, "LDS request of %zu bytes above the device limit %d", need, lim);
@@ -519,11 +523,12 @@ int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s)
     if (r->g.model == kPolymer)
         return muca_polymer_enqueue(r, sweeps, record, s);
     const Geometry &g = r->g;
-    // keep each launch's per-block u32 LDS counts below 2^32
-    const int64_t max_chunk = std::max<int64_t>(1, (int64_t)(0xFFFFFFFFll / (g.cpb / g.lpc)) - 1);
+    // the sweep count of one launch is a 32-bit argument
+    const int64_t max_chunk = 1 << 30;
+    const int64_t n_launch = (sweeps + max_chunk - 1) / max_chunk;
     int64_t done = 0;
-    while (done < sweeps) {
-        const int64_t n = std::min<int64_t>(sweeps - done, std::min<int64_t>(max_chunk, 1 << 30));
+    for (int64_t k = 0; k < n_launch; ++k) {
+        const int64_t n = (sweeps * (k + 1)) / n_launch - done;
         LatticeArgs a{};
         a.words = r->d_words;
         a.bins = r->d_bins;

@@ -19,6 +19,7 @@ struct Geometry {
     int cpb;             // threads per block
     int lpc;             // lanes per chain
     bool table_in_lds;
+    size_t lds_bytes;    // LDS of one lattice block with the table staged
     size_t off_words, off_bins, off_values, off_table, off_hist, off_energy;
     size_t ws_bytes;
 };

@@ -240,7 +240,7 @@ class Run:
 class Batch:
     """Persistent batched launches over several lattice runs (workspace tensor kept alive)."""
 
-    def __init__(self, max_runs: int, max_items: int = 8192, lanes_per_chain: int = 4,
+    def __init__(self, max_runs: int, max_items: int = 8192, lanes_per_chain: int = 0,
                  use_graph: bool = True, device="cuda"):
         import torch
         n = ctypes.c_uint64(0)

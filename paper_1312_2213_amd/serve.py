@@ -79,7 +79,7 @@ class _Active:
 
 class Server:
     def __init__(self, hbm_budget: int = 64 << 20, chain_slots: int = 1 << 16,
-                 round_site_updates: int = 1 << 16, lanes_per_chain: int = 4, use_graph: bool = True,
+                 round_site_updates: int = 1 << 16, lanes_per_chain: int = 0, use_graph: bool = True,
                  max_active: int = 256, keep_results: bool = False, stream=None):
         import torch
         self.hbm_budget = hbm_budget

@@ -32,7 +32,7 @@ def snapshot(r):
     return r.last_hist().copy(), r.lnw().copy(), s, b
 
 
-@pytest.mark.parametrize("graph,lpc", [(True, 4), (False, 4), (True, 16)])
+@pytest.mark.parametrize("graph,lpc", [(True, 4), (False, 4), (True, 16), (True, 0)])
 def test_batched_equals_plain(graph, lpc):
     import torch
     from paper_1312_2213_amd import muca
@@ -76,6 +76,28 @@ def test_batched_subset_and_regrouping():
             batch.run_iteration([batched[k] for k in grp], [MIX[k][-1] for k in grp], stream=stream)
         for k in grp:
             batched[k].merge_update()
+    for a, b in zip(plain, batched):
+        sa, sb = snapshot(a), snapshot(b)
+        assert all(np.array_equal(x, y) for x, y in zip(sa, sb))
+
+
+def test_batched_long_launch_flushes_lds_counters():
+    """A single batched launch of 3000 sweeps (64-chain work items flush
+    their 16-bit LDS counters every 1023 sweeps) equals plain launches."""
+    import torch
+    from paper_1312_2213_amd import muca
+    stream = torch.cuda.Stream()
+    specs = [("ising", 8, 2, 128, 51, 1, 3000), ("potts", 8, 3, 64, 52, 2, 1500)]
+    plain = [make(s) for s in specs]
+    batched = [make(s) for s in specs]
+    batch = muca.Batch(2, lanes_per_chain=4, use_graph=False)
+    for r, s in zip(plain, specs):
+        r.run_iteration(s[-1])
+        r.merge_update()
+    with torch.cuda.stream(stream):
+        batch.run_iteration(batched, [s[-1] for s in specs], stream=stream)
+    for r in batched:
+        r.merge_update()
     for a, b in zip(plain, batched):
         sa, sb = snapshot(a), snapshot(b)
         assert all(np.array_equal(x, y) for x, y in zip(sa, sb))

@@ -160,10 +160,29 @@ def test_ising64_full_size_sampled():
         assert np.array_equal(s[c], o.spins[c]) and b[c] == o.bins()[c]
 
 
-def test_potts48_full_size_global_table():
-    """q=8, L=48, 2048 chains: the threshold table (162 KiB) stays in global memory."""
-    o, g = pair("potts", 48, 2048, seed=33, q=8)
+@pytest.mark.parametrize("tlds", [0, 1])
+def test_potts48_full_size_table_placement(tlds):
+    """q=8, L=48, 2048 chains: the 9-column threshold table (162 KiB) read
+    from global memory, or its 8 non-trivial columns (144 KiB) staged in LDS."""
+    o, g = pair("potts", 48, 2048, seed=33, q=8, tlds=tlds)
     g.run_iteration(2)
     g.merge_update()
     assert np.array_equal(g.last_hist(), o.sweeps(2))
     assert_same_state(o, g, chains=(0, 777, 2047))
+
+
+@pytest.mark.parametrize("model,q", [("ising", 2), ("potts", 3)])
+def test_lds_counters_flushed_before_16_bit_overflow(model, q):
+    """256 chains per block, 2000 sweeps in one launch: with W = 1 every
+    Ising flip is accepted, a sweep maps s -> -s and each chain keeps its
+    energy, so one bin collects far more than 2^16 counts per block.  The
+    packed 16-bit LDS counters must be flushed in time (every 255 sweeps)."""
+    print(f"{model} flush", flush=True)
+    o, g = pair(model, 4, 256, seed=21, q=q, lpc=1, cpb=256)
+    H, _ = iterate_both(o, g, 2000, 2)
+    assert_same_state(o, g)
+    if model == "ising":
+        o2, g2 = pair(model, 4, 256, seed=21, lpc=1, cpb=256)
+        g2.run_iteration(2000)
+        g2.merge_update()
+        assert g2.last_hist().max() > 65535
