@@ -32,10 +32,13 @@ sys.path.insert(0, ROOT)
 
 # Peak 32-bit integer VALU rate of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz.
 PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
-# Algorithmic 32-bit operations per Ising attempt (counted in the design doc):
-# Philox4x32-10 10 per word (10 rounds x [2 wide multiplies + 2 three-input
-# XORs] per 4 words) + Metropolis update 13.
+# Algorithmic 32-bit operations per Ising attempt: Philox4x32-10 10 per word
+# (10 rounds x [2 wide multiplies + 2 three-input XORs] per 4 words) +
+# Metropolis update 13.
 OPS_PER_ATTEMPT = 23.0
+# HBM bytes of one 10^4-sweep launch of the Ising L=64 kernel, from the
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a device copy of known size.
+HBM_BYTES_PER_LAUNCH = 3218.125 * 1024 * 2.0 + 2386.125 * 1024
 
 
 def parse():
@@ -202,6 +205,9 @@ def bench_ising64(args):
     kern_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
     achieved = OPS_PER_ATTEMPT * attempts_per_step / (kern_ms * 1e-3)
     cycles = 2.4e9 * kern_ms * 1e-3 / (L * L * S)
+    # HBM bytes of one launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+    # of this kernel at this launch size (profiles/lattice_sweeps_ising64_hbm_counters.md)
+    traffic = HBM_BYTES_PER_LAUNCH if (S == 10000 and args.lanes_per_chain in (0, 16)) else None
 
     out = {
         "metric": "spin-flip attempts/s (MUCA iteration, 1 GPU)",
@@ -220,7 +226,8 @@ def bench_ising64(args):
                                f"seed 2, {S} sweeps per iteration, FP64 lnW, uint32 thresholds",
                    "L": L, "chains": C, "sweeps_per_iteration": S, "parallelism": "chains, 1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / PEAK_INT_OPS, "traffic": None,
+                     "unit": "TOP/s", "frac": achieved / PEAK_INT_OPS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE, copy-calibrated)",
                      "kernel": "lattice_sweeps<Ising, L=64, bit-packed>", "kernel_ms": kern_ms,
                      "ops_per_attempt": OPS_PER_ATTEMPT, "cycles_per_attempt_per_chain": cycles},
         "iterations": [{k: s[k] for k in ("iteration", "flatness", "lo_visited", "hi_visited")}
@@ -239,7 +246,11 @@ def bench_serving(args):
     reqs = [Request(id=r["id"], arrival=r["arrival"], model=r["model"], L=r["L"], q=r["q"],
                     chains=r["chains"], seed=r["seed"], max_iters=args.max_iters)
             for r in request_stream(args.requests, 4.0, 4)]
-    srv = Server(hbm_budget=64 << 20)
+    def retired(r):
+        print(f"request {r.id}: {r.iterations} iterations, flat={r.flat}, "
+              f"time to flat {r.time_to_flat:.2f} s", file=sys.stderr, flush=True)
+
+    srv = Server(hbm_budget=64 << 20, log=retired)
     t0 = time.perf_counter()
     res = srv.serve(reqs, realtime=True)
     s = summarize(res, time.perf_counter() - t0)

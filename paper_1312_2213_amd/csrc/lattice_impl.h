@@ -301,43 +301,69 @@ __device__ __forceinline__ void store_row(uint32_t *base, size_t stride, int y, 
 
 // One q-state Potts site update: proposal among the q-1 other colours,
 // dE = (neighbours equal to old) - (neighbours equal to new) unsatisfied bonds.
+// The four neighbour colours are gathered one per byte (v_perm); a byte of
+// nb ^ rep is zero exactly where the neighbour has colour rep, and the high
+// bit of each byte of ((x & 0x7F..) + 0x7F..) | x is set exactly for the
+// non-zero bytes, so both counts are population counts.  c = dE + 4 indexes
+// the threshold row: 9 columns in global memory; in LDS 8 columns, c = 8 in
+// column 4 and c = 4 (dE = 0, always accepted) not stored.  rowb is the byte
+// address of the current bin's row (LDS) or its byte offset (global).
 template <int L, int LPC, bool TLDS, int W, int X>
 __device__ __forceinline__ void potts_site(const uint32_t (&up)[W], uint32_t (&cur)[W],
-                                           const uint32_t (&dn)[W], int32_t &b, const RowRng<L, LPC, 2> &rng,
+                                           const uint32_t (&dn)[W], int32_t &rowb, const RowRng<L, LPC, 2> &rng,
                                            const uint32_t *__restrict__ T, uint32_t q)
 {
+    constexpr int w = X / 4, k = X % 4;
+    constexpr int wl = ((X + L - 1) % L) / 4, wr = ((X + 1) % L) / 4;
     const uint32_t wp = rng.template get<X, 0>();
     const uint32_t r = rng.template get<X, 1>(); // clamped in RowRng::fill
-    const uint32_t old = colour<L>(cur, X);
+    // byte 0 = down, byte 1 = up neighbour (bytes 2, 3 replaced below)
+    const uint32_t vert = __builtin_amdgcn_perm(up[w], dn[w], (uint32_t)k | ((uint32_t)(4 + k) << 8));
+    uint32_t nb;
+    if constexpr (k == 1 || k == 2) {
+        nb = __builtin_amdgcn_perm(vert, cur[w], 4u | (5u << 8) | ((uint32_t)(k - 1) << 16) | ((uint32_t)(k + 1) << 24));
+    } else if constexpr (k == 0) { // left = byte 3 of the previous word (site L-1 for X = 0)
+        const uint32_t h = __builtin_amdgcn_perm(cur[wl], cur[w], 1u | (7u << 8));
+        nb = __builtin_amdgcn_perm(vert, h, 0u | (1u << 8) | (4u << 16) | (5u << 24));
+    } else { // right = byte 0 of the next word (site 0, already updated, for X = L-1)
+        const uint32_t h = __builtin_amdgcn_perm(cur[wr], cur[w], 2u | (4u << 8));
+        nb = __builtin_amdgcn_perm(vert, h, 0u | (1u << 8) | (4u << 16) | (5u << 24));
+    }
+    const uint32_t oldrep = __builtin_amdgcn_perm(0u, cur[w], (uint32_t)k * 0x01010101u);
+    const uint32_t old = oldrep & 0xFFu;
     uint32_t nw = old + 1u + __umulhi(wp, q - 1u);
-    nw = nw >= q ? nw - q : nw;
-    const uint32_t cl = colour<L>(cur, (X + L - 1) % L);
-    const uint32_t cr = colour<L>(cur, (X + 1) % L);
-    const uint32_t cu = colour<L>(up, X);
-    const uint32_t cd = colour<L>(dn, X);
-    const int32_t n_old = (cl == old) + (cr == old) + (cu == old) + (cd == old);
-    const int32_t n_new = (cl == nw) + (cr == nw) + (cu == nw) + (cd == nw);
-    const int32_t dE = n_old - n_new;
+    nw = min(nw, nw - q); // nw - q wraps above nw when nw < q
+    const uint32_t newrep = __builtin_amdgcn_perm(0u, nw, 0u); // byte 0 of nw in every byte
+    const uint32_t xo = nb ^ oldrep, xn = nb ^ newrep;
+    const uint32_t eq_old = ~(((xo & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | xo) & 0x80808080u;
+    const uint32_t ne_new = (((xn & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | xn) & 0x80808080u;
+    const uint32_t c = (uint32_t)__builtin_popcount(ne_new) + (uint32_t)__builtin_popcount(eq_old); // dE + 4
     uint32_t t;
-    if constexpr (TLDS) // 8 staged columns: dE = -4..-1, 1..4; dE = 0 always accepts
-        t = dE == 0 ? 0xFFFFFFFFu : T[b * 8 + dE + 4 - (dE > 0 ? 1 : 0)];
-    else
-        t = T[b * 9 + dE + 4];
-    const bool acc = r < t;
-    cur[X / 4] ^= acc ? ((old ^ nw) << ((X % 4) * 8)) : 0u;
-    b += acc ? dE : 0;
+    int32_t dstep;
+    if constexpr (TLDS) {
+        const uint32_t col = (c ^ ((c >> 1) & 4u)) & 7u; // 0..3 -> 0..3, 8 -> 4, 5..7 -> 5..7
+        t = load_t<true>(T, rowb + 4 * (int32_t)col);
+        dstep = (int32_t)(c << 5) - 128;
+    } else {
+        t = load_t<false>(T, rowb + 4 * (int32_t)c);
+        dstep = (int32_t)c * 36 - 144;
+    }
+    const bool acc = (r < t) | (c == 4u);
+    const uint32_t delta = (oldrep ^ newrep) & (0xFFu << (8 * k));
+    cur[w] ^= acc ? delta : 0u;
+    rowb += acc ? dstep : 0;
 }
 
 template <int L, int LPC, bool TLDS, int W, int... X>
 __device__ __forceinline__ void potts_row(const uint32_t (&up)[W], uint32_t (&cur)[W],
-                                          const uint32_t (&dn)[W], int32_t &b,
+                                          const uint32_t (&dn)[W], int32_t &rowb,
                                           const uint32_t *__restrict__ T, uint32_t chain,
                                           uint32_t g, int y, uint32_t j, uint32_t k0, uint32_t k1, uint32_t q,
                                           std::integer_sequence<int, X...>)
 {
     RowRng<L, LPC, 2> rng;
     rng.fill(chain, g, y, j, k0, k1);
-    (potts_site<L, LPC, TLDS, W, X>(up, cur, dn, b, rng, T, q), ...);
+    (potts_site<L, LPC, TLDS, W, X>(up, cur, dn, rowb, rng, T, q), ...);
 }
 
 // ---------------------------------------------------------------------------
@@ -379,9 +405,9 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
     if constexpr (TLDS) {
         for (int i = tid; i < a.n_bins * NCL; i += blockDim.x) {
             int src = i;
-            if constexpr (MODEL == kPotts) { // skip the dE = 0 column
+            if constexpr (MODEL == kPotts) { // dE = 0 not stored; dE = +4 in column 4
                 const int bb = i >> 3, cc = i & 7;
-                src = bb * 9 + cc + (cc >= 4 ? 1 : 0);
+                src = bb * 9 + (cc == 4 ? 8 : cc);
             }
             smem[i] = a.thresholds[src];
         }
@@ -412,11 +438,18 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
             dn[w] = base[((1 % L) * W + w) * stride];
             nx[w] = base[((2 % L) * W + w) * stride];
         }
+        // the current bin's threshold row: LDS byte address of an 8-column
+        // row, or byte offset of a 9-column row in global memory
+        int32_t tbase = 0;
+        if constexpr (TLDS)
+            tbase = (int32_t)(uint32_t)(uintptr_t)(lds_u32 *)smem;
+        int32_t rowb = TLDS ? tbase + 32 * b : 36 * b;
+        auto bin_of = [&](int32_t rb) { return TLDS ? (rb - tbase) >> 5 : rb / 36; };
         for (int s = 0; s < a.n_sweeps; ++s) {
             const uint32_t g = a.g0 + (uint32_t)s;
             for (int y = 0; y < L; ++y) {
-                potts_row<L, LPC, TLDS, W>(up, cur, dn, b, T, chain, g, y, j, a.k0, a.k1, q,
-                                     std::make_integer_sequence<int, L>{});
+                potts_row<L, LPC, TLDS, W>(up, cur, dn, rowb, T, chain, g, y, j, a.k0, a.k1, q,
+                                           std::make_integer_sequence<int, L>{});
                 const int yn = (y + 3) % L;
                 if (leader) {
 #pragma unroll
@@ -431,8 +464,10 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
                     nx[w] = base[(yn * W + w) * stride];
                 }
             }
-            if (counts)
-                atomicAdd(&lhist[b >> 1], 1u << ((b & 1) << 4));
+            if (counts) {
+                const int32_t bb = bin_of(rowb);
+                atomicAdd(&lhist[bb >> 1], 1u << ((bb & 1) << 4));
+            }
             if (--until_flush == 0 && s + 1 < a.n_sweeps) {
                 until_flush = flush_every;
                 __syncthreads();
@@ -440,6 +475,7 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
                 __syncthreads();
             }
         }
+        b = bin_of(rowb);
     } else {
         constexpr int W = Row1<L>::W;
         uint32_t up[W], cur[W], dn[W], nx[W];

@@ -80,7 +80,7 @@ class _Active:
 class Server:
     def __init__(self, hbm_budget: int = 64 << 20, chain_slots: int = 1 << 16,
                  round_site_updates: int = 1 << 16, lanes_per_chain: int = 0, use_graph: bool = True,
-                 max_active: int = 256, keep_results: bool = False, stream=None):
+                 max_active: int = 256, keep_results: bool = False, stream=None, log=None):
         import torch
         self.hbm_budget = hbm_budget
         self.chain_slots = chain_slots
@@ -90,6 +90,7 @@ class Server:
         self.batch = muca.Batch(max_active, max_items=1 << 15, lanes_per_chain=lanes_per_chain,
                                 use_graph=use_graph)
         self.max_active = max_active
+        self.log = log  # called with each Result as its request retires
         self.rounds = 0
         self.peak_active = 0
         self.peak_mem = 0
@@ -160,6 +161,8 @@ class Server:
                         a.res.lnw = a.run.lnw()
                         a.res.hist = a.run.last_hist()
                     a.run.free()
+                    if self.log:
+                        self.log(a.res)
                     used_mem -= a.footprint
                     used_chains -= a.req.chains
                 else:
@@ -193,10 +196,18 @@ def run_alone(req: Request, stream=None) -> Result:
 
 
 def summarize(results: list[Result], makespan: float) -> dict:
-    ttf = np.array([r.time_to_flat for r in results])
+    """Time to flat (arrival -> merge of the first flat iteration) over the
+    requests that became flat; requests stopped by max_iters are counted
+    apart, with their time to stop."""
+    flat = np.array([r.time_to_flat for r in results if r.flat])
+    capped = np.array([r.time_to_flat for r in results if not r.flat])
     attempts = sum(r.attempts for r in results)
-    return {"requests": len(results), "flat": int(sum(r.flat for r in results)),
-            "p50_time_to_flat_s": float(np.percentile(ttf, 50)),
-            "p99_time_to_flat_s": float(np.percentile(ttf, 99)),
-            "mean_time_to_flat_s": float(ttf.mean()), "makespan_s": makespan,
+
+    def pct(a, p):
+        return float(np.percentile(a, p)) if len(a) else None
+
+    return {"requests": len(results), "flat": int(len(flat)), "capped": int(len(capped)),
+            "p50_time_to_flat_s": pct(flat, 50), "p99_time_to_flat_s": pct(flat, 99),
+            "mean_time_to_flat_s": float(flat.mean()) if len(flat) else None,
+            "p50_time_to_stop_capped_s": pct(capped, 50), "makespan_s": makespan,
             "attempts": attempts, "attempts_per_s": attempts / makespan if makespan > 0 else 0.0}
