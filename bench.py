@@ -17,7 +17,8 @@ region.  The line also carries:
 
 Other modes (--workload): "batched" (time to flat, batched vs plain),
 "serving" (200 Poisson requests, p50/p99 time to flat), "polymer" (N = 40,
-4096 chains), "copy" (device copy of known size, for counter calibration).
+4096 chains), "speedup" (statistical speedup S*_p over chains per run, Eq. 6),
+"copy" (device copy of known size, for counter calibration).
 """
 from __future__ import annotations
 
@@ -47,7 +48,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ising64",
-                    choices=["ising64", "batched", "serving", "polymer", "copy"])
+                    choices=["ising64", "batched", "serving", "polymer", "speedup", "copy"])
     ap.add_argument("--sweeps", type=int, default=10000, help="sweeps per iteration (workload: 10^4)")
     ap.add_argument("--lanes-per-chain", type=int, default=0)
     ap.add_argument("--batch-lanes-per-chain", type=int, default=0, help="batched runs: 4, 16 or 0 (per run)")
@@ -57,6 +58,7 @@ def parse():
     ap.add_argument("--batched-rounds", type=int, default=3)
     ap.add_argument("--max-iters", type=int, default=40)
     ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--systems", default="", help="speedup: comma-separated indices of the systems to run")
     return ap.parse_args()
 
 
@@ -294,6 +296,25 @@ def bench_polymer(args):
                                    "iteration, 2500 bins on [-200, 50)"}}
 
 
+def bench_speedup(args):
+    """Statistical speedup S*_p (Eq. 6) of the paper's systems: one JSON line
+    per system with N_iter to flat and to full coverage per p."""
+    from paper_1312_2213_amd import speedup as su
+    systems = su.paper_systems()
+    if args.systems:
+        systems = [systems[int(k)] for k in args.systems.split(",")]
+    for system, ps, replicas in systems:
+        print(f"== {system.name}: p = {ps}, {replicas} runs each", file=sys.stderr, flush=True)
+        res = su.run(system, ps, replicas, seed0=1, max_iters=args.max_iters,
+                     log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(json.dumps({"metric": "statistical speedup S*_p (iterations to flat at equal statistics)",
+                          "system": system.name, "replicas": replicas, "max_iters": args.max_iters,
+                          "seconds": res.seconds, "flat": res.table("n_iter"),
+                          "cover": res.table("n_cover"),
+                          "n_iter": {str(p): v for p, v in res.n_iter.items()}}), flush=True)
+    return None
+
+
 def bench_copy():
     """Device copy of 256 MiB (read 256 MiB, write 256 MiB), to scale HBM counters."""
     import torch
@@ -321,9 +342,12 @@ def main():
         out = bench_serving(args)
     elif args.workload == "polymer":
         out = bench_polymer(args)
+    elif args.workload == "speedup":
+        out = bench_speedup(args)
     else:
         out = bench_copy()
-    print(json.dumps(out), flush=True)
+    if out is not None:
+        print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

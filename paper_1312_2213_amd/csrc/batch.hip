@@ -245,6 +245,9 @@ extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, in
     // runs are raised to 16 in order of decreasing per-chain work (the
     // critical path of the launch) while all lanes still fit one resident
     // 256-thread workgroup per CU and the item list its capacity.
+    // Work items cover the run's chains only: items made of padding chains
+    // alone are not launched (padding chains are never histogrammed or read).
+    auto items_of = [&](int i, int l) { return (long)((runs[i]->cfg.n_chains + 256 / l - 1) / (256 / l)); };
     std::vector<int> lpc(n, b->lpc ? b->lpc : 4);
     if (b->lpc == 0) {
         std::vector<int> order(n);
@@ -252,8 +255,8 @@ extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, in
         for (int i = 0; i < n; ++i) {
             order[i] = i;
             if (runs[i]) {
-                lanes += (long)runs[i]->g.c_pad * 4;
-                n_items += runs[i]->g.c_pad / 64;
+                lanes += items_of(i, 4) * 256;
+                n_items += items_of(i, 4);
             }
         }
         auto work = [&](int i) {
@@ -265,7 +268,7 @@ extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, in
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
         const long cap = (long)b->n_cus * 256;
         for (int i : order) {
-            const long extra = (long)runs[i]->g.c_pad * 12, extra_items = runs[i]->g.c_pad / 16 - runs[i]->g.c_pad / 64;
+            const long extra_items = items_of(i, 16) - items_of(i, 4), extra = extra_items * 256;
             if (lanes + extra > cap || n_items + extra_items > b->max_items)
                 break;
             lanes += extra;
@@ -319,7 +322,7 @@ extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, in
         d.variant = variant_index(kind, li, tlds ? 1 : 0, lpc[i] == 16 ? 1 : 0);
         const double per_site = r->g.model == kPotts ? 2.0 : 1.0;
         const double cost = per_site * (double)r->g.n_sites * (double)sweeps[i];
-        for (int c0 = 0; c0 < r->g.c_pad; c0 += cpi)
+        for (int c0 = 0; c0 < r->cfg.n_chains; c0 += cpi)
             items.push_back({cost, i, c0});
     }
     if ((int)items.size() > b->max_items)

@@ -1,0 +1,174 @@
+"""Statistical speedup of the parallel multicanonical iteration on one GPU.
+
+The paper's time-independent measure (Eq. 6): with p independent chains per
+run and M_opt(L, p) = M_opt(L, 1) / p sweeps per chain and iteration
+(Eq. 4), the total statistics per iteration is the same for every p, and
+
+    S*_p = [N_iter M_opt(1)]_1 / [N_iter M_opt(p)]_p = p N_iter(1) / N_iter(p)
+
+where N_iter is the number of iterations until the merged histogram is flat
+(min/mean over the reachable bins above the flatness threshold), averaged
+over independent runs.  The first iteration whose histogram covers every
+reachable bin (min > 0) is recorded as a second convergence measure.  The paper finds S*_p close to p for the
+Ising model and a saturation at large p for the 8-state Potts model and for
+the multimagnetic Ising run at T = 2/3 T_c (its speedup figures; the values
+are not in the text).
+
+Here every (p, replica) run of one system starts from lnW = 0 with its own
+seed, all of them advance together (one batched persistent launch per
+round, every live run doing one iteration of its own sweep count), and a
+run retires at its first flat iteration.  Chains are thermalised only by
+the iterations themselves, as in the paper.  When the smallest p measured
+is p0 > 1, S*_p is reported relative to it: (p / p0) N_iter(p0) / N_iter(p).
+The reference p0 is the smallest p whose runs all converged: an Ising run
+of very few chains can stay at lnW = 0 for good, since with every flip
+accepted a sequential sweep maps s to -s and keeps E, so the per-sweep
+histogram of each chain holds one bin and the recursion, which links
+neighbouring bins, has nothing to link.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import muca
+from synth.workloads import m_opt
+
+BETA_C = 0.5 * math.log(1.0 + math.sqrt(2.0))  # 2D Ising critical coupling
+
+
+@dataclass
+class System:
+    model: str          # "ising", "potts" or "muma"
+    L: int
+    q: int = 2
+    beta: float = 0.0   # MUMA: fixed canonical beta of the energy factor
+    potts_law: bool = False  # use the 8-state Potts power law of Eq. 4
+
+    def sweeps(self, p: int) -> int:
+        """M_opt(L, p) = ceil(M_opt(L, 1) / p), at least one sweep."""
+        return max(1, math.ceil(m_opt(self.L, 1, self.potts_law) / p))
+
+    def config(self, p: int, seed: int, flat: float):
+        kw = {"flat_threshold": flat}
+        if self.model == "muma":
+            kw["beta"] = self.beta
+        if self.model != "potts":
+            kw["layout"] = muca.MUCA_LAYOUT_BIT
+        return muca.muca_config_default(self.model, self.L, self.q, p, seed, **kw)
+
+    @property
+    def name(self) -> str:
+        if self.model == "potts":
+            return f"{self.q}-state Potts L={self.L}"
+        if self.model == "muma":
+            return f"multimagnetic Ising L={self.L} beta={self.beta:.4f}"
+        return f"Ising L={self.L}"
+
+
+@dataclass
+class Result:
+    system: str
+    ps: list
+    sweeps: list
+    n_iter: dict = field(default_factory=dict)   # p -> N_iter per replica (None: capped)
+    n_cover: dict = field(default_factory=dict)  # p -> first iteration with every bin visited
+    trace: dict = field(default_factory=dict)    # p -> flatness of every iteration, per replica
+    seconds: float = 0.0
+
+    def table(self, measure: str = "n_iter") -> list[dict]:
+        """Mean and standard error of the measure per p; S*_p relative to
+        the smallest p whose runs all converged (None below it)."""
+        data = getattr(self, measure)
+        rows = []
+        for p, m in zip(self.ps, self.sweeps):
+            v = [x for x in data[p] if x is not None]
+            mean = float(np.mean(v)) if v else None
+            err = float(np.std(v, ddof=1) / math.sqrt(len(v))) if len(v) > 1 else None
+            rows.append({"p": p, "sweeps_per_iteration": m, "runs": len(data[p]),
+                         "capped": len(data[p]) - len(v), "mean": mean, "err": err,
+                         "speedup": None, "speedup_err": None})
+        base = next((r for r in rows if r["capped"] == 0 and r["err"] is not None), None)
+        if base is not None:
+            for r in rows[rows.index(base):]:
+                if r["mean"] is not None and r["err"] is not None:
+                    r["speedup"], r["speedup_err"] = speedup(base["p"], base["mean"], base["err"],
+                                                             r["p"], r["mean"], r["err"])
+        return rows
+
+
+def speedup(p0: int, n0: float, e0: float, p: int, n: float, e: float) -> tuple[float, float]:
+    """S*_p relative to p0 (Eq. 6 with equal total statistics per
+    iteration): (p / p0) n0 / n, with the error of the two means propagated."""
+    s = (p / p0) * n0 / n
+    rel = math.sqrt((e0 / n0) ** 2 + (e / n) ** 2) if n0 > 0 and n > 0 else float("nan")
+    return s, s * rel
+
+
+def seed_of(seed0: int, k: int, r: int) -> int:
+    """Seed of replica r of the k-th p value."""
+    return seed0 + 1000 * k + r
+
+
+def run(system: System, ps: list[int], replicas: int, seed0: int = 1, flat: float = 0.5,
+        max_iters: int = 1000, stream=None, log=None) -> Result:
+    """Runs `replicas` independent runs for every p until flat (or max_iters)."""
+    import time
+
+    import torch
+    stream = stream or torch.cuda.Stream()
+    sweeps = [system.sweeps(p) for p in ps]
+    specs = [(p, m, seed_of(seed0, k, r), r) for k, (p, m) in enumerate(zip(ps, sweeps)) for r in range(replicas)]
+    runs = []
+    with torch.cuda.stream(stream):
+        for p, _, seed, _ in specs:
+            runs.append(muca.Run(system.config(p, seed, flat), stream=stream))
+    batch = muca.Batch(len(runs), max_items=1 << 15, lanes_per_chain=0, use_graph=True)
+    res = Result(system.name, list(ps), sweeps, {p: [None] * replicas for p in ps},
+                 {p: [None] * replicas for p in ps}, {p: [[] for _ in range(replicas)] for p in ps})
+    live = list(range(len(runs)))
+    n = [0] * len(runs)
+    t0 = time.perf_counter()
+    while live:
+        with torch.cuda.stream(stream):
+            batch.run_iteration([runs[i] for i in live], [specs[i][1] for i in live], stream=stream)
+        nxt = []
+        for i in live:
+            st = runs[i].merge_update()
+            n[i] += 1
+            p, r = specs[i][0], specs[i][3]
+            res.trace[p][r].append(st["flatness"])
+            if st["flatness"] > 0 and res.n_cover[p][r] is None:
+                res.n_cover[p][r] = n[i]
+            if st["flat"] or n[i] >= max_iters:
+                res.n_iter[p][r] = n[i] if st["flat"] else None
+                runs[i].free()
+                if log:
+                    log(f"{system.name} p={specs[i][0]} seed={specs[i][2]}: "
+                        f"{n[i]} iterations{'' if st['flat'] else ' (capped)'}")
+            else:
+                nxt.append(i)
+        live = nxt
+    torch.cuda.synchronize()
+    res.seconds = time.perf_counter() - t0
+    batch.free()
+    return res
+
+
+def paper_systems() -> list[tuple[System, list[int], int]]:
+    """The systems of the paper's speedup figures (Ising; 8-state Potts with
+    its own power law; multimagnetic Ising at T = 2/3 T_c with the Ising
+    law, extrapolated as the paper does for the remaining systems), at sizes
+    whose smallest-p iterations take at most ~70 ms on one GPU:
+    (system, p values, replicas)."""
+    pw = [2 ** k for k in range(0, 13)]
+    return [
+        (System("ising", 8), pw[:11], 16),
+        (System("ising", 16), pw[:11], 16),
+        (System("ising", 24), pw[3:12], 8),
+        (System("potts", 8, q=8, potts_law=True), pw[:11], 16),
+        (System("potts", 16, q=8, potts_law=True), pw[4:12], 8),
+        (System("muma", 16, beta=1.5 * BETA_C), pw[:11], 16),
+    ]

@@ -1,0 +1,49 @@
+"""The statistical-speedup driver (batched runs of many p and seeds until
+flat) against the oracle: every run needs exactly the oracle's number of
+iterations to reach a flat histogram, since both sides run the same chains."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_trace(system, p, seed, sweeps, max_iters):
+    """Flatness of every iteration until the first flat one (or max_iters)."""
+    from oracle import oracle as orc
+    model = {"ising": orc.ISING, "potts": orc.POTTS, "muma": orc.MUMA}[system.model]
+    o = orc.LatticeRun(model, system.L, p, seed, q=system.q, beta=system.beta)
+    trace = []
+    for _ in range(max_iters):
+        _, f, _ = o.iterate(sweeps)
+        trace.append(f)
+        if f > 0.5:
+            break
+    return trace
+
+
+@pytest.mark.parametrize("spec", [("ising", 8, 2, 0.0, False), ("potts", 8, 3, 0.0, True),
+                                  ("muma", 8, 2, 0.661, False)])
+def test_iterations_to_flat_equal_the_oracle(spec):
+    from paper_1312_2213_amd import speedup as su
+    model, L, q, beta, law = spec
+    system = su.System(model, L, q=q, beta=beta, potts_law=law)
+    ps, replicas, max_iters = [4, 16, 64], 2, 120
+    print(f"{system.name}", flush=True)
+    res = su.run(system, ps, replicas, seed0=7, max_iters=max_iters)
+    flat = 0
+    for k, p in enumerate(ps):
+        for r in range(replicas):
+            want = oracle_trace(system, p, su.seed_of(7, k, r), system.sweeps(p), max_iters)
+            got = res.trace[p][r]
+            assert len(got) == len(want) and np.max(np.abs(np.subtract(got, want))) <= 1e-15, (p, r)
+            n = len(want) if want[-1] > 0.5 else None
+            assert res.n_iter[p][r] == n, (p, r)
+            flat += n is not None
+    assert flat >= 2
+    rows = res.table()
+    assert rows[0]["speedup"] == 1.0 and all(row["runs"] == replicas for row in rows)
