@@ -9,11 +9,14 @@
 // ((w >> 8) 2^-24 - 1/2) * step per axis (float), word 3 the acceptance.
 //
 // Mapping: one chain per wavefront, lane j holds bead j (N <= 64) and the
-// energy of bond (j, j+1).  For a move of bead i every lane computes its
-// pair term new - old in FP64; the terms are summed by a fixed binary tree
-// (lane k += lane k + s for s = 32, 16, ..., 1), so the sum is the same
-// number on every run.  The acceptance threshold T[b][b'] of the bin change
-// is one scalar load from the B x B matrix.
+// energy of bond (j, j+1).  At the start of a sweep lane j computes bead j's
+// proposal and the FENE energies of its new bonds (the backward one for both
+// outcomes of the previous bead's move).  For a move of bead i every lane
+// computes its pair term new - old in FP64 (the two bonded partners take the
+// precomputed bond energies); the terms are summed by a fixed binary tree
+// (lane k += lane k + s for s = 32, 16, ..., 1) built from lane permutes and
+// DPP moves, so the sum is the same number on every run.  The acceptance
+// threshold T[b][b'] of the bin change is one load from the B x B matrix.
 #include <utility>
 
 #include "muca_internal.h"
@@ -74,17 +77,57 @@ __device__ __forceinline__ float readlane_f32(float v, int lane)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// lane k receives lane k + s (s = 32, 16, ..., 1); lanes whose partner is
-// outside the wave get 0 (their sums are never read)
-__device__ __forceinline__ double from_lane_above(double v, int s)
+// Value of the next / previous lane of the wave (0 past either end); used
+// once per sweep.
+__device__ __forceinline__ float lane_above(float v)
 {
     const int lane = (int)__lane_id();
-    const int src = lane + s;
+    const float r = __int_as_float(__builtin_amdgcn_ds_bpermute(((lane + 1) & 63) * 4, __float_as_int(v)));
+    return lane < 63 ? r : 0.0f;
+}
+
+__device__ __forceinline__ float lane_below(float v)
+{
+    const int lane = (int)__lane_id();
+    const float r = __int_as_float(__builtin_amdgcn_ds_bpermute(((lane + 63) & 63) * 4, __float_as_int(v)));
+    return lane > 0 ? r : 0.0f;
+}
+
+// Lane k receives lane k + S (S = 32, 16, ..., 1) for every lane k < S; the
+// other lanes receive values that are never read.  S = 32 and 16 cross rows
+// of 16 lanes: v_permlane32_swap / v_permlane16_swap (the second result holds
+// rows 2-3 / odd rows moved down); S <= 8 stays inside a row: DPP row_shl.
+template <int S>
+__device__ __forceinline__ uint32_t from_lane_above_u32(uint32_t v)
+{
+    if constexpr (S == 32)
+        return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1];
+    else if constexpr (S == 16)
+        return __builtin_amdgcn_permlane16_swap(v, v, false, false)[1];
+    else
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + S, 0xF, 0xF, true); // row_shl:S
+}
+
+template <int S>
+__device__ __forceinline__ double from_lane_above(double v)
+{
     const uint64_t u = __double_as_longlong(v);
-    const int idx = (src < 64 ? src : lane) * 4;
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(idx, (int)(uint32_t)u);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(idx, (int)(uint32_t)(u >> 32));
-    return src < 64 ? __longlong_as_double(((uint64_t)hi << 32) | lo) : 0.0;
+    const uint32_t lo = from_lane_above_u32<S>((uint32_t)u);
+    const uint32_t hi = from_lane_above_u32<S>((uint32_t)(u >> 32));
+    return __longlong_as_double(((uint64_t)hi << 32) | lo);
+}
+
+// The fixed summation tree over 64 slots: slot k += slot k + s for
+// s = 32, 16, ..., 1; the sum ends in lane 0.
+__device__ __forceinline__ double tree_sum(double t)
+{
+    t = t + from_lane_above<32>(t);
+    t = t + from_lane_above<16>(t);
+    t = t + from_lane_above<8>(t);
+    t = t + from_lane_above<4>(t);
+    t = t + from_lane_above<2>(t);
+    t = t + from_lane_above<1>(t);
+    return t;
 }
 
 __device__ __forceinline__ int32_t energy_bin(const PolyParams &p, double E, int32_t nb)
@@ -121,56 +164,74 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
     for (int s = 0; s < a.n_sweeps; ++s) {
         const uint32_t g = a.g0 + (uint32_t)s;
         const Words4 w = philox4x32_10(chain, g, (uint32_t)j, kTagSweep, a.k0, a.k1);
+        // Bead j's proposal: no earlier move of the sweep changes bead j.
+        const float pnx = x.x + ((float)(w.w[0] >> 8) * 5.9604644775390625e-08f - 0.5f) * a.step;
+        const float pny = x.y + ((float)(w.w[1] >> 8) * 5.9604644775390625e-08f - 0.5f) * a.step;
+        const float pnz = x.z + ((float)(w.w[2] >> 8) * 5.9604644775390625e-08f - 0.5f) * a.step;
+        const uint32_t racc = min(w.w[3], 0xFFFFFFFEu); // accept iff racc < T
+        // The new bond energies of bead j's move, all known now: bead j + 1
+        // has not moved when bead j moves, and bead j - 1 sits either where
+        // the sweep found it (its move rejected) or at its proposal
+        // (accepted).  Bonds whose stretch leaves the FENE domain are flagged.
+        const float rx = lane_above(x.x), ry = lane_above(x.y), rz = lane_above(x.z);
+        const float lx = lane_below(x.x), ly = lane_below(x.y), lz = lane_below(x.z);
+        const float qx = lane_below(pnx), qy = lane_below(pny), qz = lane_below(pnz);
+        double f_fwd = 0.0, f_rej = 0.0, f_acc = 0.0;
+        uint32_t flags = 0u; // bit 0: forward broken, 1: back broken (rejected), 2: back broken (accepted)
+        if (j + 1 < N) {
+            bool br = false;
+            f_fwd = fene_energy(p, dist2(rx, ry, rz, pnx, pny, pnz), &br);
+            flags |= br ? 1u : 0u;
+        }
+        if (j >= 1 && bead) {
+            bool br = false, ba = false;
+            f_rej = fene_energy(p, dist2(lx, ly, lz, pnx, pny, pnz), &br);
+            f_acc = fene_energy(p, dist2(qx, qy, qz, pnx, pny, pnz), &ba);
+            flags |= (br ? 2u : 0u) | (ba ? 4u : 0u);
+        }
+        bool prev_acc = false;
         for (int i = 0; i < N; ++i) {
-            const uint32_t w0 = __builtin_amdgcn_readlane(w.w[0], i);
-            const uint32_t w1 = __builtin_amdgcn_readlane(w.w[1], i);
-            const uint32_t w2 = __builtin_amdgcn_readlane(w.w[2], i);
-            const uint32_t w3 = __builtin_amdgcn_readlane(w.w[3], i);
+            const float nx = readlane_f32(pnx, i), ny = readlane_f32(pny, i), nz = readlane_f32(pnz, i);
             const float xi = readlane_f32(x.x, i), yi = readlane_f32(x.y, i), zi = readlane_f32(x.z, i);
-            const float nx = xi + ((float)(w0 >> 8) * 5.9604644775390625e-08f - 0.5f) * a.step;
-            const float ny = yi + ((float)(w1 >> 8) * 5.9604644775390625e-08f - 0.5f) * a.step;
-            const float nz = zi + ((float)(w2 >> 8) * 5.9604644775390625e-08f - 0.5f) * a.step;
-            const double ub_i = readlane_f64(ub, i); // bond (i, i + 1), before the move
+            const uint32_t w3 = __builtin_amdgcn_readlane(racc, i);
+            const uint32_t fl = __builtin_amdgcn_readlane(flags, i);
+            const double fb_i = readlane_f64(prev_acc ? f_acc : f_rej, i); // new bond (i - 1, i)
+            const double ff_i = readlane_f64(f_fwd, i);                     // new bond (i, i + 1)
+            const double ub_i = readlane_f64(ub, i);                        // bond (i, i + 1), before
             const int sep = j > i ? j - i : i - j;
-            bool broken = false;
-            double en = 0.0, t = 0.0;
-            if (bead && sep != 0) {
+            double t = 0.0;
+            if (bead && sep >= 2) {
                 const double r2n = dist2(x.x, x.y, x.z, nx, ny, nz);
-                if (sep == 1) {
-                    en = fene_energy(p, r2n, &broken);
-                    const double eo = j < i ? ub : ub_i;
-                    t = en - eo;
-                } else {
-                    const double r2o = dist2(x.x, x.y, x.z, xi, yi, zi);
-                    t = lj_energy(p, r2n) - lj_energy(p, r2o);
-                }
+                const double r2o = dist2(x.x, x.y, x.z, xi, yi, zi);
+                t = lj_energy(p, r2n) - lj_energy(p, r2o);
             }
-#pragma unroll
-            for (int st = 32; st >= 1; st >>= 1)
-                t = t + from_lane_above(t, st);
-            const double dE = readlane_f64(t, 0);
-            const bool any_broken = __builtin_amdgcn_ballot_w64(broken) != 0ull;
+            if (j == i + 1)
+                t = ff_i - ub_i;
+            if (j == i - 1)
+                t = fb_i - ub;
+            const double dE = readlane_f64(tree_sum(t), 0);
+            const bool any_broken = (i + 1 < N && (fl & 1u)) || (i >= 1 && (fl & (prev_acc ? 4u : 2u)));
             const double En = E + dE;
             const int32_t bn = energy_bin(p, En, a.n_bins);
             bool acc = false;
             if (!any_broken && bn >= 0) {
                 const uint32_t T = a.thresholds[(size_t)b * B + (uint32_t)bn];
-                acc = min(w3, 0xFFFFFFFEu) < T;
+                acc = w3 < T;
             }
             if (acc) {
-                const double en_right = readlane_f64(en, i + 1 < N ? i + 1 : i); // new bond (i, i + 1)
                 if (j == i) {
                     x.x = nx;
                     x.y = ny;
                     x.z = nz;
                     if (i + 1 < N)
-                        ub = en_right;
+                        ub = ff_i;
                 }
                 if (j == i - 1)
-                    ub = en; // new bond (i - 1, i)
+                    ub = fb_i;
                 E = En;
                 b = bn;
             }
+            prev_acc = acc;
         }
         if (counts)
             atomicAdd(&lhist[b], 1u);
