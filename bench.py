@@ -157,17 +157,43 @@ def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int =
         run_batched.flat = flat
         return time.perf_counter() - t0, ttf, n, runs
 
+    def run_served():
+        """The serving loop with every instance present at t = 0: rounds of
+        equal site updates per chain, so a long iteration spans several
+        rounds while short instances finish theirs every round."""
+        from paper_1312_2213_amd.serve import Request, Server
+        reqs = []
+        for k, (c, sw) in enumerate(specs):
+            cfg = muca.muca_config.from_buffer_copy(c)
+            if max_iters is None:
+                cfg.flat_threshold = 2.0  # fixed number of iterations: never flat
+            reqs.append(Request(id=k, arrival=0.0, model="lattice", L=c.L, q=c.q, chains=c.n_chains,
+                                seed=c.seed, max_iters=rounds if max_iters is None else max_iters,
+                                sweeps_per_iter=sw, cfg=cfg))
+        srv = Server(hbm_budget=1 << 40, chain_slots=1 << 20, lanes_per_chain=batch_lpc,
+                     keep_results=True, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = srv.serve(reqs, realtime=False)
+        return time.perf_counter() - t0, [r.time_to_flat for r in res], [r.iterations for r in res], res
+
     tb, ttf_b, it_b, runs_b = run_batched()
+    ts, ttf_s, it_s, res_s = run_served()
     tp, ttf_p, it_p, runs_p = run_plain()
     same = all((a.last_hist() == b.last_hist()).all() for a, b in zip(runs_b, runs_p))
+    same_served = all((r.hist == b.last_hist()).all() and r.iterations == n
+                      for r, b, n in zip(res_s, runs_p, it_p))
     attempts = sum(c.n_chains * c.L * c.L * sw * k for (c, sw), k in zip(specs, it_b))
     out = {"instances": "potts q=8 L=16,24,32,48 x 2048 chains + 4 x muma L=32 x 512 chains (beta 0.5)",
            "sweeps_per_iteration": [sw for _, sw in specs], "iterations": it_b,
-           "batched_s": tb, "plain_s": tp, "speedup": tp / tb,
-           "batched_attempts_per_s": attempts / tb, "plain_attempts_per_s": attempts / tp,
-           "identical_histograms": bool(same)}
+           "batched_s": tb, "served_s": ts, "plain_s": tp, "speedup": tp / tb, "served_speedup": tp / ts,
+           "batched_attempts_per_s": attempts / tb, "served_attempts_per_s": attempts / ts,
+           "plain_attempts_per_s": attempts / tp,
+           "identical_histograms": bool(same), "served_identical_histograms": bool(same_served)}
     if max_iters is not None:
         out.update({"time_to_flat_batched_s": ttf_b, "time_to_flat_plain_s": ttf_p,
+                    "time_to_flat_served_s": ttf_s,
+                    "mean_time_to_flat_served_s": sum(ttf_s) / len(ttf_s),
                     "flat": run_batched.flat,
                     "mean_time_to_flat_batched_s": sum(ttf_b) / len(ttf_b),
                     "mean_time_to_flat_plain_s": sum(ttf_p) / len(ttf_p)})

@@ -41,8 +41,11 @@ class Request:
     flat_threshold: float = 0.5
     max_iters: int = 1000
     sweeps_per_iter: int = 0
+    cfg: object = None  # a complete muca_config (e.g. a MUMA run's beta); overrides the fields above
 
     def config(self):
+        if self.cfg is not None:
+            return self.cfg
         kw = {"flat_threshold": self.flat_threshold, "layout": muca.MUCA_LAYOUT_BIT if self.model == "ising"
               else muca.MUCA_LAYOUT_AUTO}
         return muca.muca_config_default(self.model, self.L, self.q, self.chains, self.seed, **kw)

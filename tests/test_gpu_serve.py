@@ -9,10 +9,16 @@ pytestmark = pytest.mark.gpu
 
 def reqs():
     from paper_1312_2213_amd.serve import Request
+    from paper_1312_2213_amd import muca
     spec = [("ising", 16, 2, 256), ("potts", 16, 4, 320), ("ising", 24, 2, 128),
             ("potts", 16, 8, 192), ("ising", 8, 2, 64), ("potts", 32, 2, 256)]
-    return [Request(id=k, arrival=0.002 * k, model=m, L=L, q=q, chains=c, seed=500 + k, max_iters=4)
-            for k, (m, L, q, c) in enumerate(spec)]
+    out = [Request(id=k, arrival=0.002 * k, model=m, L=L, q=q, chains=c, seed=500 + k, max_iters=4)
+           for k, (m, L, q, c) in enumerate(spec)]
+    # a request given as a complete configuration (multimagnetic, beta = 0.5)
+    cfg = muca.muca_config_default("muma", 16, 2, 192, 507, beta=0.5)
+    out.append(Request(id=len(out), arrival=0.003, model="muma", L=16, q=2, chains=192, seed=507,
+                       max_iters=4, sweeps_per_iter=40, cfg=cfg))
+    return out
 
 
 def test_each_result_same_alone_and_in_the_mix():
