@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--max-iters", type=int, default=40)
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--systems", default="", help="speedup: comma-separated indices of the systems to run")
+    ap.add_argument("--round-site-updates", type=int, default=1 << 16,
+                    help="serving: site updates per chain in one round")
     return ap.parse_args()
 
 
@@ -278,14 +280,15 @@ def bench_serving(args):
         print(f"request {r.id}: {r.iterations} iterations, flat={r.flat}, "
               f"time to flat {r.time_to_flat:.2f} s", file=sys.stderr, flush=True)
 
-    srv = Server(hbm_budget=64 << 20, log=retired)
+    srv = Server(hbm_budget=64 << 20, round_site_updates=args.round_site_updates, log=retired)
     t0 = time.perf_counter()
     res = srv.serve(reqs, realtime=True)
     s = summarize(res, time.perf_counter() - t0)
     s.update({"metric": "time-to-flat-histogram p50/p99 and aggregate attempts/s (serving, 1 GPU)",
               "workload": f"{args.requests} Poisson requests at 4/s, seed 4; Ising L in {{16..64}} or "
                           "Potts q in {2..10}, L in {16,32}; 256-2048 chains; flatness 0.5; "
-                          f"max {args.max_iters} iterations; HBM budget 64 MiB",
+                          f"max {args.max_iters} iterations; HBM budget 64 MiB; "
+                          f"{args.round_site_updates} site updates per chain and round",
               "rounds": srv.rounds, "peak_active": srv.peak_active})
     return s
 

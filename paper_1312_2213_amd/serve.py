@@ -16,7 +16,8 @@ Chunking only moves launch boundaries, so every request's result is
 bit-identical to running it alone.
 
 Sweeps per iteration follow the paper's M_opt(L, p) power laws (Eq. 4) for
-p = 1, divided over the request's chains (at least 10).
+p = 1, divided over the request's chains (at least 10): the Ising law for
+Ising and q = 2 Potts, the 8-state Potts law for Potts q >= 3.
 """
 from __future__ import annotations
 
@@ -52,7 +53,11 @@ class Request:
 
     def __post_init__(self):
         if not self.sweeps_per_iter:
-            potts_fit = self.model == "potts" and self.q >= 5
+            # Potts bins are one per unit of unsatisfied bonds: for q >= 3
+            # nearly all 2N + 1 are reachable, four times the Ising count,
+            # so the Ising law would leave too few samples per bin to pass
+            # the flatness test; q >= 3 takes the 8-state Potts law.
+            potts_fit = self.model == "potts" and self.q >= 3
             self.sweeps_per_iter = sweeps_per_iteration(self.L, self.chains, potts_fit)
 
 

@@ -33,3 +33,16 @@ def test_workload_table():
     inst = WORKLOADS["potts8_batched"]["instances"]
     assert sum(i["chains"] for i in inst if i["model"] == "potts") == 8192
     assert sum(i["chains"] for i in inst if i["model"] == "muma") == 2048
+
+
+def test_served_requests_take_the_potts_law_for_q_at_least_3():
+    """Potts bins are one per unit of unsatisfied bonds (about four times
+    the Ising count for q >= 3): those requests take the 8-state Potts law."""
+    import math
+    from paper_1312_2213_amd.serve import Request
+    r4 = Request(id=0, arrival=0.0, model="potts", L=32, q=4, chains=256, seed=1)
+    assert r4.sweeps_per_iter == math.ceil(24 * 32 ** 2.67 / 256)
+    r2 = Request(id=1, arrival=0.0, model="potts", L=32, q=2, chains=256, seed=1)
+    assert r2.sweeps_per_iter == math.ceil(5.7 * 32 ** 2.51 / 256)
+    ri = Request(id=2, arrival=0.0, model="ising", L=64, q=2, chains=2048, seed=1)
+    assert ri.sweeps_per_iter == math.ceil(5.7 * 64 ** 2.51 / 2048)
