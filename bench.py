@@ -56,7 +56,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched_vs_plain sub-object")
     ap.add_argument("--batched-rounds", type=int, default=3)
-    ap.add_argument("--max-iters", type=int, default=40)
+    ap.add_argument("--max-iters", type=int, default=None,
+                    help="iteration cap (default: 40 batched, 3000 serving, 1000 speedup)")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--systems", default="", help="speedup: comma-separated indices of the systems to run")
     ap.add_argument("--round-site-updates", type=int, default=1 << 16,
@@ -363,6 +364,8 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
         sys.exit(2)
+    if args.max_iters is None:
+        args.max_iters = {"serving": 3000, "speedup": 1000}.get(args.workload, 40)
     if args.workload == "ising64":
         out = bench_ising64(args)
     elif args.workload == "batched":

@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MUCA_ABI_VERSION 1u
+#define MUCA_ABI_VERSION 2u
 
 typedef enum muca_status {
     MUCA_OK = 0,
@@ -83,6 +83,12 @@ typedef struct muca_config {
     float step;             /* side of the displacement cube                   */
     int32_t lanes_per_chain; /* lattice: 0 = auto, else 1, 2, 4 or 16 lanes share
                                 one chain's random-number work                 */
+    int32_t chain0;         /* global index of the run's first chain: its chains
+                               are numbered chain0 .. chain0 + n_chains - 1 in the
+                               random-number counters, so a run of C chains can
+                               be split into shards of consecutive chains (one
+                               per device) that together give the unsplit run;
+                               0 for a standalone run, >= 0                    */
 } muca_config;
 
 typedef struct muca_iter_stats {
@@ -133,6 +139,23 @@ int muca_thermalize(muca_run *run, int64_t sweeps, void *stream);
  * lnW^(n+1), builds and uploads the new thresholds, clears H.  MUCA_E_STATE
  * if no sweeps were enqueued since the last merge. */
 int muca_merge_update(muca_run *run, muca_iter_stats *out);
+
+/* Sharded runs (one run per device, each a consecutive range of the global
+ * chains, all with the same seed and weights; parallel-scheme paragraph:
+ * the histograms of all realisations are merged and every part continues
+ * with the same new weights).
+ *   muca_get_pending_hist: copies the histogram accumulated by
+ *     muca_run_iteration since the last merge (n = number of bins) to
+ *     host memory h, after waiting for the run's stream; the run is unchanged.
+ *     MUCA_E_STATE without sweeps since the last merge.
+ *   muca_merge_update_hist: muca_merge_update with a caller-supplied merged
+ *     histogram (the sum of every shard's pending histogram, e.g. from an
+ *     all-reduce); the run's own pending histogram is discarded.  Every shard
+ *     calling it with the same h gets the same weights and thresholds, so the
+ *     shards stay the unsplit run bit for bit.  Errors as muca_merge_update;
+ *     MUCA_E_ARG if n differs from the number of bins. */
+int muca_get_pending_hist(const muca_run *run, uint64_t *h, int64_t n);
+int muca_merge_update_hist(muca_run *run, const uint64_t *h, int64_t n, muca_iter_stats *out);
 
 /* Reweighting (Eq. 2) of the last merged pair (H^(n), lnW^(n)).
  * Energy ensembles: for each beta[k], out[4k..4k+3] = { <E>/N, beta^2

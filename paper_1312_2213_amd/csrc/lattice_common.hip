@@ -43,7 +43,7 @@ __global__ void lattice_init(LatticeInitArgs a)
                 if (x >= L)
                     break;
                 const int i = y * L + x;
-                const Words4 r = philox4x32_10((uint32_t)c, 0u, (uint32_t)(i >> 2), kTagInit, a.k0, a.k1);
+                const Words4 r = philox4x32_10((uint32_t)(a.chain0 + c), 0u, (uint32_t)(i >> 2), kTagInit, a.k0, a.k1);
                 const uint32_t v = r.w[i & 3];
                 uint32_t code;
                 if (a.model == kPotts)

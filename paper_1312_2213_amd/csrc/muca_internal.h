@@ -37,6 +37,7 @@ struct LatticeInitArgs {
     int32_t c_pad;
     int32_t L, q, lo, step;
     int32_t model, layout;
+    int32_t chain0; // global index of chain 0 in the random-number counters
 };
 
 // Arguments of one polymer sweep launch (one chain per wavefront).
@@ -49,6 +50,7 @@ struct PolymerArgs {
     unsigned long long *hist;   // [n_bins]
     uint32_t k0, k1, g0;
     int32_t n_sweeps, n_chains, c_pad, n_bins, n_beads, record, chains_per_block;
+    int32_t chain0;             // global index of chain 0 in the random-number counters
     float step;
 };
 

@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
     double ub = (j < N - 1) ? bond[j] : 0.0; // energy of bond (j, j + 1)
     double E = a.energy[c];
     int32_t b = a.bins[c];
-    const uint32_t chain = (uint32_t)c;
+    const uint32_t chain = (uint32_t)(a.chain0 + c);
     const bool counts = a.record && c < a.n_chains && j == 0;
     const uint32_t B = (uint32_t)a.n_bins;
 

@@ -223,6 +223,7 @@ int muca_polymer_enqueue(muca_run *r, int64_t sweeps, bool record, hipStream_t s
         a.n_beads = r->cfg.n_beads;
         a.record = record ? 1 : 0;
         a.chains_per_block = g.cpb;
+        a.chain0 = r->cfg.chain0;
         a.step = r->cfg.step;
         hipError_t e = launch_polymer_sweeps(a, k, s);
         if (e != hipSuccess) {

@@ -67,6 +67,9 @@ int muca_geometry(const muca_config *c, Geometry *g)
         return muca_fail(MUCA_E_ARG, "abi_version %u, library has %u", c->abi_version, MUCA_ABI_VERSION);
     if (c->n_chains < 1)
         return muca_fail(MUCA_E_ARG, "n_chains must be >= 1");
+    if (c->chain0 < 0 || (int64_t)c->chain0 + c->n_chains > 0x7FFFFFFFll)
+        return muca_fail(MUCA_E_ARG, "chain0 %d with %d chains outside the 31-bit chain numbering", c->chain0,
+                         c->n_chains);
     std::memset(g, 0, sizeof *g);
     g->model = c->model;
     g->c_pad = (c->n_chains + 63) / 64 * 64;
@@ -490,6 +493,7 @@ extern "C" int muca_init(const muca_config *c, void *d_ws, uint64_t ws_bytes, co
     a.step = g.step;
     a.model = g.model;
     a.layout = g.layout;
+    a.chain0 = c->chain0;
     hipError_t e = launch_lattice_init(a, r->stream);
     if (e == hipSuccess)
         e = launch_fill_u64(r->d_hist, g.n_bins, r->stream);
@@ -544,7 +548,7 @@ int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s)
         a.q = r->cfg.q;
         a.record = record ? 1 : 0;
         a.table_in_lds = g.table_in_lds ? 1 : 0;
-        a.chain0 = 0;
+        a.chain0 = r->cfg.chain0;
         HIP_OR_POISON(r, launch_lattice_sweeps(g.model, g.L, g.layout, g.lpc, g.cpb, a, s));
         r->sweep += (uint32_t)n;
         done += n;
@@ -630,6 +634,35 @@ extern "C" int muca_merge_update(muca_run *r, muca_iter_stats *st)
     HIP_OR_POISON(r, hipMemcpy(H.data(), r->d_hist, (size_t)B * 8u, hipMemcpyDeviceToHost));
     HIP_OR_POISON(r, launch_fill_u64(r->d_hist, B, r->stream));
     return muca_finish_iteration(r, H.data(), st);
+}
+
+extern "C" int muca_get_pending_hist(const muca_run *r_, uint64_t *h, int64_t n)
+{
+    muca_run *r = const_cast<muca_run *>(r_);
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (!h || n != r->g.n_bins)
+        return muca_fail(MUCA_E_ARG, "need a host array of n_bins = %d entries", r->g.n_bins);
+    if (r->pending <= 0)
+        return muca_fail(MUCA_E_STATE, "no sweeps since the last merge");
+    HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
+    HIP_OR_POISON(r, hipMemcpy(h, r->d_hist, (size_t)n * 8u, hipMemcpyDeviceToHost));
+    return MUCA_OK;
+}
+
+extern "C" int muca_merge_update_hist(muca_run *r, const uint64_t *h, int64_t n, muca_iter_stats *st)
+{
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (!h || n != r->g.n_bins)
+        return muca_fail(MUCA_E_ARG, "need a merged histogram of n_bins = %d entries", r->g.n_bins);
+    if (r->pending <= 0)
+        return muca_fail(MUCA_E_STATE, "merge_update without sweeps since the last merge");
+    HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
+    HIP_OR_POISON(r, launch_fill_u64(r->d_hist, r->g.n_bins, r->stream));
+    return muca_finish_iteration(r, h, st);
 }
 
 extern "C" int muca_reweight(const muca_run *r, const double *betas, int32_t n, double *out)

@@ -20,7 +20,7 @@ _LIB_PATH = os.path.join(_HERE, "libmuca.so")
 
 MUCA_ISING, MUCA_POTTS, MUCA_MUMA, MUCA_POLYMER = 0, 1, 2, 3
 MUCA_LAYOUT_AUTO, MUCA_LAYOUT_BIT, MUCA_LAYOUT_BYTE = 0, 1, 2
-MUCA_ABI_VERSION = 1
+MUCA_ABI_VERSION = 2
 MODELS = {"ising": MUCA_ISING, "potts": MUCA_POTTS, "muma": MUCA_MUMA, "polymer": MUCA_POLYMER}
 
 
@@ -40,7 +40,7 @@ class muca_config(ctypes.Structure):
                 ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double),
                 ("lj_eps", ctypes.c_double), ("lj_sigma", ctypes.c_double), ("lj_rcut", ctypes.c_double),
                 ("fene_k", ctypes.c_double), ("fene_r0", ctypes.c_double), ("fene_R", ctypes.c_double),
-                ("step", ctypes.c_float), ("lanes_per_chain", ctypes.c_int32)]
+                ("step", ctypes.c_float), ("lanes_per_chain", ctypes.c_int32), ("chain0", ctypes.c_int32)]
 
 
 class muca_iter_stats(ctypes.Structure):
@@ -66,6 +66,8 @@ def _load():
         "muca_run_iteration": (ctypes.c_int, [vp, i64, vp]),
         "muca_thermalize": (ctypes.c_int, [vp, i64, vp]),
         "muca_merge_update": (ctypes.c_int, [vp, P(muca_iter_stats)]),
+        "muca_get_pending_hist": (ctypes.c_int, [vp, vp, i64]),
+        "muca_merge_update_hist": (ctypes.c_int, [vp, vp, i64, P(muca_iter_stats)]),
         "muca_reweight": (ctypes.c_int, [vp, vp, i32, vp]),
         "muca_batch_workspace_bytes": (ctypes.c_int, [i32, i32, P(ctypes.c_uint64)]),
         "muca_batch_create": (ctypes.c_int, [i32, i32, i32, i32, vp, u64, P(vp)]),
@@ -93,7 +95,8 @@ def _load():
 
 LIB = _load()
 EXPORTED = ("muca_config_default", "muca_workspace_bytes", "muca_init", "muca_run_iteration",
-            "muca_thermalize", "muca_merge_update", "muca_reweight", "muca_batch_workspace_bytes",
+            "muca_thermalize", "muca_merge_update", "muca_get_pending_hist", "muca_merge_update_hist",
+            "muca_reweight", "muca_batch_workspace_bytes",
             "muca_batch_create", "muca_batch_run_iteration", "muca_batch_free", "muca_autotune", "muca_sizes", "muca_get_lnw", "muca_get_last_hist",
             "muca_get_thresholds", "muca_get_chain_state", "muca_set_lnw", "muca_set_thresholds",
             "muca_checkpoint", "muca_restore", "muca_free", "muca_last_error")
@@ -165,6 +168,19 @@ class Run:
     def merge_update(self) -> dict:
         st = muca_iter_stats()
         _check(LIB.muca_merge_update(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def pending_hist(self) -> np.ndarray:
+        """Histogram of the sweeps since the last merge (a shard's part)."""
+        h = np.zeros(self.n_bins, np.uint64)
+        _check(LIB.muca_get_pending_hist(self.handle, _ptr(h), len(h)))
+        return h
+
+    def merge_update_hist(self, h) -> dict:
+        """Merge step with the histogram summed over all shards of a run."""
+        h = np.ascontiguousarray(h, np.uint64)
+        st = muca_iter_stats()
+        _check(LIB.muca_merge_update_hist(self.handle, _ptr(h), len(h), ctypes.byref(st)))
         return st.as_dict()
 
     def reweight(self, betas) -> np.ndarray:

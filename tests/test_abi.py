@@ -50,3 +50,16 @@ def test_host_only_calls_without_gpu():
     bad = muca.muca_config_default("ising", 8, 2, 16, 1, lo=-126)
     with pytest.raises(muca.MucaError):
         muca.muca_workspace_bytes(bad)
+    # shards: chain0 numbers a run's chains inside a larger run; negative or
+    # past the 31-bit chain numbering is rejected
+    assert c.chain0 == 0 and c.abi_version == muca.MUCA_ABI_VERSION
+    for chain0, ok in ((0, True), (4096, True), (-1, False), (0x7FFFFFFF - 15, False)):
+        s = muca.muca_config_default("ising", 8, 2, 16, 1, chain0=chain0)
+        if ok:
+            assert muca.muca_workspace_bytes(s) > 0
+        else:
+            with pytest.raises(muca.MucaError):
+                muca.muca_workspace_bytes(s)
+    old = muca.muca_config_default("ising", 8, 2, 16, 1, abi_version=1)
+    with pytest.raises(muca.MucaError):
+        muca.muca_workspace_bytes(old)

@@ -46,4 +46,6 @@ def test_iterations_to_flat_equal_the_oracle(spec):
             flat += n is not None
     assert flat >= 2
     rows = res.table()
-    assert rows[0]["speedup"] == 1.0 and all(row["runs"] == replicas for row in rows)
+    assert all(row["runs"] == replicas for row in rows)
+    ref = [row for row in rows if row["speedup"] is not None]
+    assert not ref or ref[0]["speedup"] == 1.0
