@@ -17,7 +17,8 @@ region.  The line also carries:
 
 Other modes (--workload): "batched" (time to flat, batched vs plain),
 "serving" (200 Poisson requests, p50/p99 time to flat), "polymer" (N = 40,
-4096 chains), "speedup" (statistical speedup S*_p over chains per run, Eq. 6),
+4096 chains), "polymer_paper" (the paper's homopolymer, N = 40 and 80),
+"speedup" (statistical speedup S*_p over chains per run, Eq. 6),
 "copy" (device copy of known size, for counter calibration).
 """
 from __future__ import annotations
@@ -48,7 +49,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ising64",
-                    choices=["ising64", "batched", "serving", "polymer", "speedup", "copy"])
+                    choices=["ising64", "batched", "serving", "polymer", "polymer_paper", "speedup", "copy"])
     ap.add_argument("--sweeps", type=int, default=10000, help="sweeps per iteration (workload: 10^4)")
     ap.add_argument("--lanes-per-chain", type=int, default=0)
     ap.add_argument("--batch-lanes-per-chain", type=int, default=0, help="batched runs: 4, 16 or 0 (per run)")
@@ -294,14 +295,30 @@ def bench_serving(args):
     return s
 
 
-def bench_polymer(args):
+def bench_polymer_paper(args):
+    """The paper's homopolymer (Eq. 7 with its parameters, no LJ cutoff) at
+    N = 40 and 80, 4096 chains: one JSON line each."""
+    from synth import PAPER_POLYMER
+    pp = dict(PAPER_POLYMER)
+    for N in (40, 80):
+        out = bench_polymer(args, N=N, params=dict(pp, x_lo=-400.0, x_hi=100.0, n_bins=1000),
+                            walk=dict(bond=pp["fene_r0"], min_dist=pp["lj_sigma"]))
+        out["metric"] = "polymer displacement attempts/s, the paper's homopolymer (1 GPU)"
+        out["config"] = {"workload": f"bead-spring homopolymer with the paper's parameters (K=40, r0=0.7, "
+                                     f"r_max=1, sigma=2^(-1/6) r0, LJ uncut), N={N}, 4096 chains, seed 5, "
+                                     "1000 sweeps per iteration, 1000 bins on [-400, 100)"}
+        print(json.dumps(out), flush=True)
+    return None
+
+
+def bench_polymer(args, N=40, params=None, walk=None):
     import numpy as np
     import torch
     from paper_1312_2213_amd import muca
     from synth import polymer_walk
-    C, N, S = 4096, 40, 1000
-    pos = polymer_walk(N, C, 5)
-    cfg = muca.muca_config_default("polymer", 0, 2, C, 5, n_beads=N)
+    C, S = 4096, 1000
+    pos = polymer_walk(N, C, 5, **(walk or {}))
+    cfg = muca.muca_config_default("polymer", 0, 2, C, 5, n_beads=N, **(params or {}))
     stream = torch.cuda.current_stream()
     run = muca.Run(cfg, positions=pos, stream=stream)
     run.run_iteration(S)
@@ -374,6 +391,8 @@ def main():
         out = bench_serving(args)
     elif args.workload == "polymer":
         out = bench_polymer(args)
+    elif args.workload == "polymer_paper":
+        out = bench_polymer_paper(args)
     elif args.workload == "speedup":
         out = bench_speedup(args)
     else:

@@ -592,23 +592,31 @@ int orc_polymer_init(const orc_polymer *p, const float *pos, double *E, int32_t 
     return 0;
 }
 
+/* the new-minus-old energy of the pair (i, j) when bead i moves to xn */
+static double pair_delta(const orc_polymer *p, const float *pos, int32_t i, int32_t j,
+                         const float *xn, int *broken)
+{
+    double en, eo;
+    if (j >= p->n_beads || j == i)
+        return 0.0;
+    en = pair_energy(p, i, j, dist2(xn, pos + 3 * j), broken);
+    eo = pair_energy(p, i, j, dist2(pos + 3 * i, pos + 3 * j), broken);
+    return en - eo;
+}
+
 /* dE of moving bead i to xn: per-partner terms summed by a fixed binary
  * tree over 64 slots (slot j holds partner j's term, zero for j == i and
- * j >= n_beads): for stride 32, 16, ..., 1, slot k += slot k + stride. */
+ * j >= n_beads; for n_beads > 64 slot j holds partner j's term plus partner
+ * j + 64's term): for stride 32, 16, ..., 1, slot k += slot k + stride. */
 static double polymer_delta(const orc_polymer *p, const float *pos, int32_t i,
                             const float *xn, int *broken)
 {
     double t[64];
     int32_t j, stride;
     for (j = 0; j < 64; ++j) {
-        t[j] = 0.0;
-        if (j >= p->n_beads || j == i)
-            continue;
-        {
-            double en = pair_energy(p, i, j, dist2(xn, pos + 3 * j), broken);
-            double eo = pair_energy(p, i, j, dist2(pos + 3 * i, pos + 3 * j), broken);
-            t[j] = en - eo;
-        }
+        t[j] = pair_delta(p, pos, i, j, xn, broken);
+        if (p->n_beads > 64)
+            t[j] = t[j] + pair_delta(p, pos, i, j + 64, xn, broken);
     }
     for (stride = 32; stride >= 1; stride /= 2)
         for (j = 0; j < stride; ++j)

@@ -8,8 +8,8 @@
 // Philox(c, g, i, SWEEP): words 0..2 give the displacement
 // ((w >> 8) 2^-24 - 1/2) * step per axis (float), word 3 the acceptance.
 //
-// Mapping: one chain per wavefront, lane j holds bead j (N <= 64) and the
-// energy of bond (j, j+1).  At the start of a sweep lane j computes bead j's
+// Mapping: one chain per wavefront, lane j holds bead j and the energy of
+// bond (j, j+1), and for 64 < N <= 128 also bead j + 64 and its bond.  At the start of a sweep lane j computes bead j's
 // proposal and the FENE energies of its new bonds (the backward one for both
 // outcomes of the previous bead's move).  For a move of bead i every lane
 // computes its pair term new - old in FP64 (the two bonded partners take the
@@ -77,22 +77,6 @@ __device__ __forceinline__ float readlane_f32(float v, int lane)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// Value of the next / previous lane of the wave (0 past either end); used
-// once per sweep.
-__device__ __forceinline__ float lane_above(float v)
-{
-    const int lane = (int)__lane_id();
-    const float r = __int_as_float(__builtin_amdgcn_ds_bpermute(((lane + 1) & 63) * 4, __float_as_int(v)));
-    return lane < 63 ? r : 0.0f;
-}
-
-__device__ __forceinline__ float lane_below(float v)
-{
-    const int lane = (int)__lane_id();
-    const float r = __int_as_float(__builtin_amdgcn_ds_bpermute(((lane + 63) & 63) * 4, __float_as_int(v)));
-    return lane > 0 ? r : 0.0f;
-}
-
 // Lane k receives lane k + S (S = 32, 16, ..., 1) for every lane k < S; the
 // other lanes receive values that are never read.  S = 32 and 16 cross rows
 // of 16 lanes: v_permlane32_swap / v_permlane16_swap (the second result holds
@@ -140,6 +124,16 @@ __device__ __forceinline__ int32_t energy_bin(const PolyParams &p, double E, int
     return (int32_t)f;
 }
 
+// Value of lane `src` of the wave (once per sweep).
+__device__ __forceinline__ float from_lane(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(v)));
+}
+
+// One chain per wavefront.  Lane j holds bead j and, with TWO (64 < N <= 128),
+// bead j + 64 (register set 1).  A pair sum slot is lane j's term plus, with
+// TWO, the term of bead j + 64.
+template <bool TWO>
 __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams p)
 {
     extern __shared__ uint32_t lhist[];
@@ -147,68 +141,112 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
         lhist[i] = 0u;
     __syncthreads();
 
+    constexpr int NS = TWO ? 2 : 1; // beads per lane
+    constexpr int SLOTS = 64 * NS;  // bead slots per chain in memory
     const int j = (int)(threadIdx.x & 63u);
     const int c = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const int N = a.n_beads;
-    const bool bead = j < N;
-    float4 *pos = a.pos + (size_t)c * 64;
-    double *bond = a.bond + (size_t)c * 64;
-    float4 x = bead ? pos[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-    double ub = (j < N - 1) ? bond[j] : 0.0; // energy of bond (j, j + 1)
+    float4 *pos = a.pos + (size_t)c * SLOTS;
+    double *bond = a.bond + (size_t)c * SLOTS;
+    float4 x[NS];
+    double ub[NS]; // energy of bond (bead, bead + 1)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int bd = j + 64 * s;
+        x[s] = bd < N ? pos[bd] : make_float4(0.f, 0.f, 0.f, 0.f);
+        ub[s] = bd < N - 1 ? bond[bd] : 0.0;
+    }
     double E = a.energy[c];
     int32_t b = a.bins[c];
     const uint32_t chain = (uint32_t)(a.chain0 + c);
     const bool counts = a.record && c < a.n_chains && j == 0;
     const uint32_t B = (uint32_t)a.n_bins;
+    const int up_l = (j + 1) & 63, dn_l = (j + 63) & 63;
 
-    for (int s = 0; s < a.n_sweeps; ++s) {
-        const uint32_t g = a.g0 + (uint32_t)s;
-        const Words4 w = philox4x32_10(chain, g, (uint32_t)j, kTagSweep, a.k0, a.k1);
-        // Bead j's proposal: no earlier move of the sweep changes bead j.
-        const float pnx = x.x + ((float)(w.w[0] >> 8) * 5.9604644775390625e-08f - 0.5f) * a.step;
-        const float pny = x.y + ((float)(w.w[1] >> 8) * 5.9604644775390625e-08f - 0.5f) * a.step;
-        const float pnz = x.z + ((float)(w.w[2] >> 8) * 5.9604644775390625e-08f - 0.5f) * a.step;
-        const uint32_t racc = min(w.w[3], 0xFFFFFFFEu); // accept iff racc < T
-        // The new bond energies of bead j's move, all known now: bead j + 1
-        // has not moved when bead j moves, and bead j - 1 sits either where
+    for (int s_ = 0; s_ < a.n_sweeps; ++s_) {
+        const uint32_t g = a.g0 + (uint32_t)s_;
+        float pnx[NS], pny[NS], pnz[NS];
+        uint32_t racc[NS], flags[NS];
+        double f_fwd[NS], f_rej[NS], f_acc[NS];
+        // Each bead's proposal: no earlier move of the sweep changes the bead.
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const Words4 w = philox4x32_10(chain, g, (uint32_t)(j + 64 * s), kTagSweep, a.k0, a.k1);
+            pnx[s] = x[s].x + ((float)(w.w[0] >> 8) * 5.9604644775390625e-08f - 0.5f) * a.step;
+            pny[s] = x[s].y + ((float)(w.w[1] >> 8) * 5.9604644775390625e-08f - 0.5f) * a.step;
+            pnz[s] = x[s].z + ((float)(w.w[2] >> 8) * 5.9604644775390625e-08f - 0.5f) * a.step;
+            racc[s] = min(w.w[3], 0xFFFFFFFEu); // accept iff racc < T
+        }
+        // The new bond energies of each bead's move, all known now: bead + 1
+        // has not moved when the bead moves, and bead - 1 sits either where
         // the sweep found it (its move rejected) or at its proposal
         // (accepted).  Bonds whose stretch leaves the FENE domain are flagged.
-        const float rx = lane_above(x.x), ry = lane_above(x.y), rz = lane_above(x.z);
-        const float lx = lane_below(x.x), ly = lane_below(x.y), lz = lane_below(x.z);
-        const float qx = lane_below(pnx), qy = lane_below(pny), qz = lane_below(pnz);
-        double f_fwd = 0.0, f_rej = 0.0, f_acc = 0.0;
-        uint32_t flags = 0u; // bit 0: forward broken, 1: back broken (rejected), 2: back broken (accepted)
-        if (j + 1 < N) {
-            bool br = false;
-            f_fwd = fene_energy(p, dist2(rx, ry, rz, pnx, pny, pnz), &br);
-            flags |= br ? 1u : 0u;
+        float rx[NS], ry[NS], rz[NS], lx[NS], ly[NS], lz[NS], qx[NS], qy[NS], qz[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            rx[s] = from_lane(x[s].x, up_l), ry[s] = from_lane(x[s].y, up_l), rz[s] = from_lane(x[s].z, up_l);
+            lx[s] = from_lane(x[s].x, dn_l), ly[s] = from_lane(x[s].y, dn_l), lz[s] = from_lane(x[s].z, dn_l);
+            qx[s] = from_lane(pnx[s], dn_l), qy[s] = from_lane(pny[s], dn_l), qz[s] = from_lane(pnz[s], dn_l);
         }
-        if (j >= 1 && bead) {
-            bool br = false, ba = false;
-            f_rej = fene_energy(p, dist2(lx, ly, lz, pnx, pny, pnz), &br);
-            f_acc = fene_energy(p, dist2(qx, qy, qz, pnx, pny, pnz), &ba);
-            flags |= (br ? 2u : 0u) | (ba ? 4u : 0u);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int bd = j + 64 * s;
+            // bead + 1 is in the next lane of the same set, or lane 0 of the next set
+            const int rs = (j == 63) ? s + 1 : s;
+            // bead - 1 is in the previous lane of the same set, or lane 63 of the previous set
+            const int ls = (j == 0) ? s - 1 : s;
+            f_fwd[s] = f_rej[s] = f_acc[s] = 0.0;
+            flags[s] = 0u; // bit 0: forward broken, 1: back broken (rejected), 2: back broken (accepted)
+            if (bd + 1 < N && rs < NS) {
+                bool br = false;
+                const float ax = rs == s ? rx[s] : rx[NS - 1], ay = rs == s ? ry[s] : ry[NS - 1],
+                            az = rs == s ? rz[s] : rz[NS - 1];
+                f_fwd[s] = fene_energy(p, dist2(ax, ay, az, pnx[s], pny[s], pnz[s]), &br);
+                flags[s] |= br ? 1u : 0u;
+            }
+            if (bd >= 1 && bd < N && ls >= 0) {
+                bool br = false, ba = false;
+                const float ax = ls == s ? lx[s] : lx[0], ay = ls == s ? ly[s] : ly[0], az = ls == s ? lz[s] : lz[0];
+                const float bx = ls == s ? qx[s] : qx[0], by = ls == s ? qy[s] : qy[0], bz = ls == s ? qz[s] : qz[0];
+                f_rej[s] = fene_energy(p, dist2(ax, ay, az, pnx[s], pny[s], pnz[s]), &br);
+                f_acc[s] = fene_energy(p, dist2(bx, by, bz, pnx[s], pny[s], pnz[s]), &ba);
+                flags[s] |= (br ? 2u : 0u) | (ba ? 4u : 0u);
+            }
         }
         bool prev_acc = false;
         for (int i = 0; i < N; ++i) {
-            const float nx = readlane_f32(pnx, i), ny = readlane_f32(pny, i), nz = readlane_f32(pnz, i);
-            const float xi = readlane_f32(x.x, i), yi = readlane_f32(x.y, i), zi = readlane_f32(x.z, i);
-            const uint32_t w3 = __builtin_amdgcn_readlane(racc, i);
-            const uint32_t fl = __builtin_amdgcn_readlane(flags, i);
-            const double fb_i = readlane_f64(prev_acc ? f_acc : f_rej, i); // new bond (i - 1, i)
-            const double ff_i = readlane_f64(f_fwd, i);                     // new bond (i, i + 1)
-            const double ub_i = readlane_f64(ub, i);                        // bond (i, i + 1), before
-            const int sep = j > i ? j - i : i - j;
+            const int li = i & 63;
+            const bool hi = TWO && i >= 64; // the moving bead's register set
+            auto pick = [&](auto v0, auto v1) { return hi ? v1 : v0; };
+            const float nx = readlane_f32(pick(pnx[0], pnx[NS - 1]), li);
+            const float ny = readlane_f32(pick(pny[0], pny[NS - 1]), li);
+            const float nz = readlane_f32(pick(pnz[0], pnz[NS - 1]), li);
+            const float xi = readlane_f32(pick(x[0].x, x[NS - 1].x), li);
+            const float yi = readlane_f32(pick(x[0].y, x[NS - 1].y), li);
+            const float zi = readlane_f32(pick(x[0].z, x[NS - 1].z), li);
+            const uint32_t w3 = __builtin_amdgcn_readlane(pick(racc[0], racc[NS - 1]), li);
+            const uint32_t fl = __builtin_amdgcn_readlane(pick(flags[0], flags[NS - 1]), li);
+            const double fb_i = readlane_f64(prev_acc ? pick(f_acc[0], f_acc[NS - 1]) : pick(f_rej[0], f_rej[NS - 1]),
+                                             li);                       // new bond (i - 1, i)
+            const double ff_i = readlane_f64(pick(f_fwd[0], f_fwd[NS - 1]), li); // new bond (i, i + 1)
+            const double ub_i = readlane_f64(pick(ub[0], ub[NS - 1]), li);       // bond (i, i + 1), before
             double t = 0.0;
-            if (bead && sep >= 2) {
-                const double r2n = dist2(x.x, x.y, x.z, nx, ny, nz);
-                const double r2o = dist2(x.x, x.y, x.z, xi, yi, zi);
-                t = lj_energy(p, r2n) - lj_energy(p, r2o);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int bd = j + 64 * s;
+                const int sep = bd > i ? bd - i : i - bd;
+                double ts = 0.0;
+                if (bd < N && sep >= 2) {
+                    const double r2n = dist2(x[s].x, x[s].y, x[s].z, nx, ny, nz);
+                    const double r2o = dist2(x[s].x, x[s].y, x[s].z, xi, yi, zi);
+                    ts = lj_energy(p, r2n) - lj_energy(p, r2o);
+                }
+                if (bd == i + 1)
+                    ts = ff_i - ub_i;
+                if (bd == i - 1)
+                    ts = fb_i - ub[s];
+                t = s == 0 ? ts : t + ts;
             }
-            if (j == i + 1)
-                t = ff_i - ub_i;
-            if (j == i - 1)
-                t = fb_i - ub;
             const double dE = readlane_f64(tree_sum(t), 0);
             const bool any_broken = (i + 1 < N && (fl & 1u)) || (i >= 1 && (fl & (prev_acc ? 4u : 2u)));
             const double En = E + dE;
@@ -219,15 +257,19 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
                 acc = w3 < T;
             }
             if (acc) {
-                if (j == i) {
-                    x.x = nx;
-                    x.y = ny;
-                    x.z = nz;
-                    if (i + 1 < N)
-                        ub = ff_i;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const int bd = j + 64 * s;
+                    if (bd == i) {
+                        x[s].x = nx;
+                        x[s].y = ny;
+                        x[s].z = nz;
+                        if (i + 1 < N)
+                            ub[s] = ff_i;
+                    }
+                    if (bd == i - 1)
+                        ub[s] = fb_i;
                 }
-                if (j == i - 1)
-                    ub = fb_i;
                 E = En;
                 b = bn;
             }
@@ -236,10 +278,14 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
         if (counts)
             atomicAdd(&lhist[b], 1u);
     }
-    if (bead)
-        pos[j] = x;
-    if (j < N - 1)
-        bond[j] = ub;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int bd = j + 64 * s;
+        if (bd < N)
+            pos[bd] = x[s];
+        if (bd < N - 1)
+            bond[bd] = ub[s];
+    }
     if (j == 0) {
         a.energy[c] = E;
         a.bins[c] = b;
@@ -269,7 +315,10 @@ hipError_t launch_polymer_sweeps(const PolymerArgs &a, const PolymerConsts &k, h
     if (chains_per_block < 1 || chains_per_block > 4 || a.c_pad % chains_per_block)
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)(a.c_pad / chains_per_block)), block((unsigned)(64 * chains_per_block));
-    hipLaunchKernelGGL(polymer_sweeps, grid, block, (size_t)a.n_bins * 4u, s, a, p);
+    if (a.n_beads > 64)
+        hipLaunchKernelGGL(polymer_sweeps<true>, grid, block, (size_t)a.n_bins * 4u, s, a, p);
+    else
+        hipLaunchKernelGGL(polymer_sweeps<false>, grid, block, (size_t)a.n_bins * 4u, s, a, p);
     return hipGetLastError();
 }
 

@@ -38,8 +38,8 @@ static PolymerConsts consts_of(const muca_config *c)
 
 int muca_polymer_geometry(const muca_config *c, Geometry *g)
 {
-    if (c->n_beads < 2 || c->n_beads > 64)
-        return muca_fail(MUCA_E_ARG, "n_beads %d outside 2..64", c->n_beads);
+    if (c->n_beads < 2 || c->n_beads > 128)
+        return muca_fail(MUCA_E_ARG, "n_beads %d outside 2..128", c->n_beads);
     if (c->n_bins < 2 || c->n_bins > 8192 || !(c->x_hi > c->x_lo))
         return muca_fail(MUCA_E_ARG, "bad energy binning (%d bins on [%g, %g))", c->n_bins, c->x_lo, c->x_hi);
     if (!(c->fene_R > 0.0) || !(c->lj_rcut > 0.0) || !(c->lj_sigma > 0.0) || !(c->step > 0.0f))
@@ -52,12 +52,15 @@ int muca_polymer_geometry(const muca_config *c, Geometry *g)
         return muca_fail(MUCA_E_ARG, "polymer chains_per_block %d outside 1..4", g->cpb);
     while (g->c_pad % g->cpb)
         g->cpb /= 2;
-    g->lpc = 64;
+    // bead slots per chain: lane j of the chain's wavefront holds bead j
+    // (and bead j + 64 when n_beads > 64)
+    g->lpc = c->n_beads > 64 ? 128 : 64;
+    const size_t S = (size_t)g->lpc;
     size_t off = 0;
     g->off_words = off; // positions, float4 per bead slot
-    off = align256(off + (size_t)g->c_pad * 64 * 16);
-    g->off_energy = off; // bond energies [c_pad][64] then running energies [c_pad]
-    off = align256(off + (size_t)g->c_pad * 64 * 8 + (size_t)g->c_pad * 8);
+    off = align256(off + (size_t)g->c_pad * S * 16);
+    g->off_energy = off; // bond energies [c_pad][S] then running energies [c_pad]
+    off = align256(off + (size_t)g->c_pad * S * 8 + (size_t)g->c_pad * 8);
     g->off_bins = off;
     off = align256(off + (size_t)g->c_pad * 4);
     g->off_values = off;
@@ -118,23 +121,24 @@ int muca_polymer_init(muca_run *r, const float *h_pos)
         return muca_fail(MUCA_E_ARG, "polymer runs need initial positions");
     const PolymerConsts k = consts_of(c);
     const int N = c->n_beads, C = c->n_chains;
-    std::vector<float> pos((size_t)g.c_pad * 64 * 4, 0.0f);
-    std::vector<double> bond((size_t)g.c_pad * 64 + g.c_pad, 0.0);
+    const size_t S = (size_t)g.lpc;
+    std::vector<float> pos((size_t)g.c_pad * S * 4, 0.0f);
+    std::vector<double> bond((size_t)g.c_pad * S + g.c_pad, 0.0);
     std::vector<int32_t> bins(g.c_pad, 0);
-    double *energy = bond.data() + (size_t)g.c_pad * 64;
+    double *energy = bond.data() + (size_t)g.c_pad * S;
     for (int ch = 0; ch < g.c_pad; ++ch) {
         // padding chains copy chain 0: valid states, never histogrammed
         const float *src = h_pos + (size_t)(ch < C ? ch : 0) * N * 3;
         for (int j = 0; j < N; ++j)
             for (int a = 0; a < 3; ++a)
-                pos[((size_t)ch * 64 + j) * 4 + a] = src[3 * j + a];
+                pos[((size_t)ch * S + j) * 4 + a] = src[3 * j + a];
         bool broken = false;
         double e = 0.0;
         for (int i = 0; i < N; ++i)
             for (int j = i + 1; j < N; ++j)
                 e += pair_energy(c, k, i, j, d2(src + 3 * i, src + 3 * j), &broken);
         for (int j = 0; j + 1 < N; ++j)
-            bond[(size_t)ch * 64 + j] = pair_energy(c, k, j, j + 1, d2(src + 3 * j, src + 3 * j + 3), &broken);
+            bond[(size_t)ch * S + j] = pair_energy(c, k, j, j + 1, d2(src + 3 * j, src + 3 * j + 3), &broken);
         energy[ch] = e;
         bins[ch] = broken ? -1 : bin_of(c, k, e);
         if (bins[ch] < 0)
@@ -209,7 +213,7 @@ int muca_polymer_enqueue(muca_run *r, int64_t sweeps, bool record, hipStream_t s
         PolymerArgs a{};
         a.pos = (float4 *)r->d_words;
         a.bond = r->d_energy;
-        a.energy = r->d_energy + (size_t)g.c_pad * 64;
+        a.energy = r->d_energy + (size_t)g.c_pad * g.lpc;
         a.bins = r->d_bins;
         a.thresholds = r->d_table;
         a.hist = r->d_hist;
@@ -243,16 +247,17 @@ int muca_polymer_state(muca_run *r, int32_t chain0, int32_t count, float *pos, i
     if (e == hipSuccess && bins && count)
         e = hipMemcpy(bins, r->d_bins + chain0, (size_t)count * 4, hipMemcpyDeviceToHost);
     if (e == hipSuccess && energy && count)
-        e = hipMemcpy(energy, r->d_energy + (size_t)g.c_pad * 64 + chain0, (size_t)count * 8,
+        e = hipMemcpy(energy, r->d_energy + (size_t)g.c_pad * g.lpc + chain0, (size_t)count * 8,
                       hipMemcpyDeviceToHost);
     if (e == hipSuccess && pos && count) {
-        std::vector<float> p((size_t)count * 64 * 4);
-        e = hipMemcpy(p.data(), (const float *)r->d_words + (size_t)chain0 * 64 * 4, p.size() * 4,
+        const size_t S = (size_t)g.lpc;
+        std::vector<float> p((size_t)count * S * 4);
+        e = hipMemcpy(p.data(), (const float *)r->d_words + (size_t)chain0 * S * 4, p.size() * 4,
                       hipMemcpyDeviceToHost);
         for (int k = 0; k < count && e == hipSuccess; ++k)
             for (int j = 0; j < r->cfg.n_beads; ++j)
                 for (int a = 0; a < 3; ++a)
-                    pos[((size_t)k * r->cfg.n_beads + j) * 3 + a] = p[((size_t)k * 64 + j) * 4 + a];
+                    pos[((size_t)k * r->cfg.n_beads + j) * 3 + a] = p[((size_t)k * S + j) * 4 + a];
     }
     if (e != hipSuccess) {
         r->poisoned = true;

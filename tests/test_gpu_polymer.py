@@ -71,3 +71,53 @@ def test_polymer_full_size_sampled():
     H = o.sweeps(2)
     assert np.array_equal(g.last_hist(), H)
     check_state(o, g, chains=(0, 1, 63, 64, 2048, 4095))
+
+
+def pair_paper(n_beads, chains, seed, lnw_slope=None):
+    """The paper's homopolymer (Eq. 7 with its K, r0, r_max; sigma = 2^(-1/6)
+    r0; no LJ cutoff); 1000 bins of 0.5 on [-400, 100)."""
+    import torch  # noqa: F401
+    from oracle import oracle as orc
+    from paper_1312_2213_amd import muca
+    from synth import PAPER_POLYMER
+    pp = dict(PAPER_POLYMER)
+    rng = dict(x_lo=-400.0, x_hi=100.0, n_bins=1000)
+    pos = polymer_walk(n_beads, chains, seed, bond=pp["fene_r0"], min_dist=pp["lj_sigma"])
+    o = orc.PolymerRun(n_beads=n_beads, n_chains=chains, seed=seed, pos=pos, **rng, **pp)
+    cfg = muca.muca_config_default("polymer", 0, 2, chains, seed, n_beads=n_beads, **rng, **pp)
+    g = muca.Run(cfg, positions=pos)
+    if lnw_slope is not None:
+        lnw = lnw_slope * o.bin_centres()
+        o.lnW = np.array(lnw, np.float64)
+        g.set_lnw(lnw)
+    return o, g
+
+
+@pytest.mark.parametrize("N", [40, 80, 128])
+def test_paper_polymer_sweeps(N):
+    """N = 80 and 128 take the two-beads-per-lane kernel (slot j = term of
+    partner j + term of partner j + 64, then the 64-slot tree)."""
+    print(f"paper polymer N={N}", flush=True)
+    o, g = pair_paper(N, 67, 21, lnw_slope=-0.8)
+    for it in range(2):
+        H = o.sweeps(12)
+        o.advance(12)
+        o.merge_update(H)
+        g.run_iteration(12)
+        g.merge_update()
+        assert np.array_equal(g.last_hist(), H), it
+        assert np.allclose(g.lnw(), o.lnW, rtol=0, atol=1e-12), it
+    check_state(o, g)
+
+
+def test_paper_polymer_iterations_with_recursion():
+    o, g = pair_paper(80, 64, 22)
+    for it in range(3):
+        H = o.sweeps(10)
+        o.advance(10)
+        o.merge_update(H)
+        g.run_iteration(10)
+        g.merge_update()
+        assert np.array_equal(g.last_hist(), H), it
+        assert np.allclose(g.lnw(), o.lnW, rtol=0, atol=1e-12), it
+    check_state(o, g)

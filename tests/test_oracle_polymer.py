@@ -91,3 +91,57 @@ def test_dimer_bond_length_distribution(orc):
     assert H[:2000].sum() == 0
     ratio = (Hw / Hw.sum()) / (ww / ww.sum())
     assert np.abs(ratio[:3] - 1).max() < 0.03, ratio
+
+
+def paper_run(orc, N, C, seed):
+    from synth import PAPER_POLYMER
+    pp = dict(PAPER_POLYMER)
+    pos = polymer_walk(N, C, seed, bond=pp["fene_r0"], min_dist=pp["lj_sigma"])
+    return orc.PolymerRun(n_beads=N, n_chains=C, seed=seed, pos=pos, x_lo=-400.0, x_hi=100.0,
+                          n_bins=1000, **pp), pos
+
+
+def test_paper_parameters_closed_form(orc):
+    """Eq. 7 with the paper's parameters: LJ minimum -1 at r0 (sigma =
+    2^(-1/6) r0, no cutoff, no shift), FENE zero at r0 and infinite at
+    r_max = 1."""
+    r, _ = paper_run(orc, 40, 1, 3)
+    s = 2 ** (-1 / 6) * 0.7
+    # trimer with the ends at r0: bonds at r0 too (equilateral), LJ(r0) = -1
+    h = math.sqrt(0.75) * 0.7
+    tri = np.array([[0, 0, 0], [0.35, h, 0], [0.7, 0, 0]], np.float32)
+    x = tri.astype(float)
+    d = np.linalg.norm(x[2] - x[0])
+    lj = 4 * ((s / d) ** 12 - (s / d) ** 6)
+    fene = sum(-(40 / 2) * 0.09 * math.log(1 - ((np.linalg.norm(x[k + 1] - x[k]) - 0.7) / 0.3) ** 2)
+               for k in range(2))
+    assert abs(r.energy(tri) - (lj + fene)) < 1e-9 and abs(lj + 1.0) < 1e-5
+    # straight 4-bead chain at spacing r0: every non-bonded pair interacts,
+    # also the ends at 3 r0 = 3.4 sigma (no cutoff)
+    line = np.array([[0.7 * k, 0, 0] for k in range(4)], np.float32)
+    x = line.astype(float)
+    want = 0.0
+    for a_, b_ in ((0, 2), (1, 3), (0, 3)):
+        rr = np.linalg.norm(x[b_] - x[a_])
+        want += 4 * ((s / rr) ** 12 - (s / rr) ** 6)
+    for k in range(3):
+        t = (np.linalg.norm(x[k + 1] - x[k]) - 0.7) / 0.3
+        want += -(40 / 2) * 0.09 * math.log(1 - t * t)
+    assert abs(r.energy(line) - want) < 1e-12 and want < -0.02
+    assert r.energy(np.array([[0, 0, 0], [1.0, 0, 0]], np.float32)) == math.inf
+
+
+@pytest.mark.parametrize("N", [40, 80])
+def test_paper_polymer_running_energy(orc, N):
+    """The per-move energy change (for N > 64 each tree slot first adds the
+    terms of partners j and j + 64) keeps the running energy equal to the
+    recomputed total energy."""
+    r, pos = paper_run(orc, N, 3, 11)
+    r.lnW = -0.5 * r.bin_centres()
+    r.sweeps(60, record=False)
+    r.advance(60)
+    for c in range(3):
+        e = r.energy(r.pos[c])
+        assert abs(e - r.E[c]) < 1e-9 * max(1.0, abs(e))
+        assert r.bin[c] == r.bin_of(r.E[c])
+    assert not np.array_equal(r.pos, pos)
