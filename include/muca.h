@@ -208,7 +208,7 @@ int muca_sizes(const muca_run *run, int32_t *n_bins, int32_t *n_cols, int32_t *n
 int muca_get_lnw(const muca_run *run, double *h_lnw, int32_t n_bins);
 int muca_get_last_hist(const muca_run *run, uint64_t *h_hist, int32_t n_bins);
 int muca_get_thresholds(const muca_run *run, uint32_t *h_t, int64_t count);
-/* Lattice: spins[count][N] int8 (Ising/MUMA +-1, Potts colour), bins[count].
+/* Lattice: spins[count][N] bytes (Ising/MUMA int8 +-1, Potts uint8 colour 0..q-1), bins[count].
  * Polymer: positions[count][n_beads][3] float into `state`, energies[count]
  * double into `energy`.  Either output may be NULL. */
 int muca_get_chain_state(const muca_run *run, int32_t chain0, int32_t count, void *state,

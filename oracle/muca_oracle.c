@@ -184,7 +184,7 @@ void orc_measure(const orc_lattice *c, const int8_t *s, int32_t *E, int32_t *M)
     measure(c, s, E, M);
 }
 
-/* spins[chain][site]: Ising/MUMA +-1, Potts colour 0..q-1 */
+/* spins[chain][site]: Ising/MUMA +-1, Potts colour 0..q-1 (as unsigned bytes) */
 void orc_init_lattice(const orc_lattice *c, int8_t *spins, int32_t *E, int32_t *M)
 {
     int32_t N = c->L * c->L, ch, i;
@@ -295,8 +295,11 @@ int orc_sweeps(const orc_lattice *c, int8_t *spins, int32_t *E, int32_t *M,
                 nb[2] = s[site(L, y + 1, x)];
                 nb[3] = s[site(L, y - 1, x)];
                 if (c->model == ORC_POTTS) {
+                    /* colours 0..q-1 (q <= 255) are stored as unsigned bytes */
                     uint32_t wp, wa;
-                    int32_t old = s[i], nw, n_old = 0, n_new = 0, k, dE;
+                    int32_t old = (uint8_t)s[i], nw, n_old = 0, n_new = 0, k, dE;
+                    for (k = 0; k < 4; ++k)
+                        nb[k] = (uint8_t)nb[k];
                     if ((i & 1) == 0)
                         draw(c->seed, (uint32_t)ch, g, (uint32_t)(i >> 1), ORC_TAG_SWEEP, w);
                     wp = w[2 * (i & 1)];

@@ -175,7 +175,8 @@ class LatticeRun:
                            self.lo, self.hi, self.beta)
         B = self.n_bins
         N = self.L * self.L
-        self.spins = np.zeros((self.n_chains, N), np.int8)
+        # Potts colours 0..q-1 are unsigned bytes; Ising / MUMA spins are +-1
+        self.spins = np.zeros((self.n_chains, N), np.uint8 if self.model == POTTS else np.int8)
         self.E = np.zeros(self.n_chains, np.int32)
         self.M = np.zeros(self.n_chains, np.int32)
         lib().orc_init_lattice(ctypes.byref(self._c), _ptr(self.spins, ctypes.c_int8),

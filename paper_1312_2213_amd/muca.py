@@ -226,7 +226,8 @@ class Run:
         if self.cfg.model == MUCA_POLYMER:
             state = np.zeros((count, self.cfg.n_beads, 3), np.float32)
         else:
-            state = np.zeros((count, self.n_sites), np.int8)
+            # Ising / MUMA spins +-1 (int8); Potts colours 0..q-1 (uint8)
+            state = np.zeros((count, self.n_sites), np.uint8 if self.cfg.model == MUCA_POTTS else np.int8)
         _check(LIB.muca_get_chain_state(self.handle, chain0, count, _ptr(state), _ptr(bins), _ptr(energy)))
         return state, bins, energy
 

@@ -186,3 +186,45 @@ def test_lds_counters_flushed_before_16_bit_overflow(model, q):
         g2.run_iteration(2000)
         g2.merge_update()
         assert g2.last_hist().max() > 65535
+
+
+def test_potts_maximum_q():
+    """q = 255: colours up to 254 (high bit set) take the general byte test."""
+    o, g = pair("potts", 8, 70, seed=255, q=255)
+    iterate_both(o, g, 6, 3)
+    assert_same_state(o, g)
+    assert o.spins.max() >= 128
+
+
+@pytest.mark.parametrize("model,L,q", [("ising", 4, 2), ("potts", 4, 3), ("muma", 4, 2), ("potts", 64, 4)])
+def test_smallest_and_largest_lattices(model, L, q):
+    print(f"{model} L={L} q={q}", flush=True)
+    o, g = pair(model, L, 97, seed=40 + L, q=q, beta=0.5)
+    iterate_both(o, g, 8 if L < 64 else 2, 2)
+    assert_same_state(o, g)
+
+
+def test_many_chains_sampled():
+    """65536 chains (the whole chip at 1 lane per chain): merged histogram and
+    sampled chains after 2 sweeps."""
+    o, g = pair("ising", 16, 65536, seed=6, layout=1)
+    g.run_iteration(2)
+    g.merge_update()
+    assert np.array_equal(g.last_hist(), o.sweeps(2))
+    s, b, _ = g.chain_state()
+    for c in (0, 1, 4095, 4096, 65535):
+        assert np.array_equal(s[c], o.spins[c]) and b[c] == o.bins()[c]
+
+
+def test_argument_errors_leave_the_run_usable():
+    from paper_1312_2213_amd import muca
+    _, g = pair("ising", 8, 64, seed=3)
+    for bad in (0, -5):
+        with pytest.raises(muca.MucaError):
+            g.run_iteration(bad)
+    with pytest.raises(muca.MucaError):
+        g.merge_update()  # nothing to merge yet
+    with pytest.raises(muca.MucaError):
+        g.set_lnw(np.zeros(3))  # wrong length
+    g.run_iteration(3)
+    assert g.merge_update()["samples"] == 64 * 3

@@ -199,3 +199,26 @@ def test_reweight_muma_exact(orc):
     assert abs(out[0] - (pm * np.abs(Ms)).sum() / z / 16) < 1e-12
     assert abs(out[1] - (pm * Ms ** 2).sum() / z / 256) < 1e-12
     assert abs(out[2]) < 1e-12
+
+
+def test_potts_colours_stay_below_q_for_large_q(orc):
+    """Colours 0..q-1 are unsigned bytes (q up to 255): with lnW = 0 every
+    proposal is accepted, so after a few sweeps every proposal map, including
+    the wrap from q-1 past 0, has been applied; colours stay in [0, q), every
+    site changed colour, and the running E equals the recomputed one."""
+    import numpy as np
+    q = 255
+    o = orc.LatticeRun(orc.POTTS, 8, 4, 31, q=q)
+    assert o.spins.dtype == np.uint8
+    before = o.spins.copy()
+    o.sweeps(1)
+    o.advance(1)
+    assert np.all(o.spins != before)  # every attempt accepted: a different colour
+    o.sweeps(40)
+    o.advance(40)
+    assert o.spins.max() < q and o.spins.max() >= 200
+    for c in range(4):
+        E = 0
+        s = o.spins[c].reshape(8, 8).astype(int)
+        E += int(np.sum(s != np.roll(s, -1, 1)) + np.sum(s != np.roll(s, -1, 0)))
+        assert E == o.E[c]
