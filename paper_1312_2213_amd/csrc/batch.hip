@@ -268,6 +268,8 @@ extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, in
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
         const long cap = (long)b->n_cus * 256;
         for (int i : order) {
+            if (runs[i]->g.model == kPotts && runs[i]->g.L % 16)
+                continue; // Potts rows split over the lanes: 16 lanes need L a multiple of 16
             const long extra_items = items_of(i, 16) - items_of(i, 4), extra = extra_items * 256;
             if (lanes + extra > cap || n_items + extra_items > b->max_items)
                 break;

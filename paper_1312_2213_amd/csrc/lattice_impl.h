@@ -366,14 +366,6 @@ __device__ __forceinline__ void potts_row(const uint32_t (&up)[W], uint32_t (&cu
     (potts_site<L, LPC, TLDS, W, X>(up, cur, dn, rowb, rng, T, q), ...);
 }
 
-// ---------------------------------------------------------------------------
-// One block of chains: threads [0, blockDim) handle chains
-// [c_first, c_first + blockDim / LPC) of the instance described by `a`.
-// The threshold table is staged into LDS (TLDS) and the block's histogram is
-// accumulated in LDS, then added to the instance's global histogram.
-// Used by the plain kernel (one launch per instance) and by the persistent
-// batched kernel (one block per work item).
-// ---------------------------------------------------------------------------
 // Adds the block's packed LDS counters to the global histogram and clears
 // them.  Called by every thread of the block between two barriers.
 __device__ __forceinline__ void flush_hist(uint32_t *lhist, int hw, unsigned long long *hist)
@@ -390,6 +382,289 @@ __device__ __forceinline__ void flush_hist(uint32_t *lhist, int hw, unsigned lon
     }
 }
 
+// ---------------------------------------------------------------------------
+// Potts with the per-site work split over the lanes of a chain.  Lane j of
+// the chain's LPC lanes owns the S = L / LPC consecutive sites [S j, S j + S)
+// of every row: it keeps only its segment of rows y-1, y, y+1 (bytes 0..S-1
+// of its segment words), draws the Philox words of its sites, and computes
+// for each of them the threshold column for both outcomes of the left
+// neighbour's attempt.  The right, up and down neighbours do not change
+// before a site's own attempt, except the right neighbour of the row's last
+// site (site 0, decided first), for which both variants are kept.  The
+// attempts then run through the row on all lanes of the chain in lockstep:
+// each takes its site's descriptor from the owning lane (DPP), selects by the
+// previous outcome, reads the threshold and compares.  At the end of the row
+// every lane applies the accepted proposals to its own segment and stores it
+// (byte stores when segments are not word-aligned); a lane only reads back
+// bytes it wrote itself.
+// ---------------------------------------------------------------------------
+template <int L, int LPC>
+struct PottsLP {
+    static constexpr bool ok = (LPC == 4 || LPC == 16) && L % LPC == 0;
+    static constexpr int S = L / LPC;       // sites per lane
+    static constexpr int SW = (S + 3) / 4;  // words of a lane's segment
+    static constexpr int NCALL = S / 2 + 1; // Philox calls that cover S sites from any first site
+};
+
+// value of lane O of the chain's lane group
+template <int LPC, int O>
+__device__ __forceinline__ uint32_t group_bcast(uint32_t v)
+{
+    if constexpr (LPC == 4)
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, O * 0x55, 0xF, 0xF, false);
+    else
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x150 + O, 0xF, 0xF, false);
+}
+
+// value of the previous / next lane of the group, cyclic
+template <int LPC>
+__device__ __forceinline__ uint32_t group_prev(uint32_t v)
+{
+    if constexpr (LPC == 4)
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x93, 0xF, 0xF, false); // quad_perm [3,0,1,2]
+    else
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x121, 0xF, 0xF, false); // row_ror:1
+}
+
+template <int LPC>
+__device__ __forceinline__ uint32_t group_next(uint32_t v)
+{
+    if constexpr (LPC == 4)
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x39, 0xF, 0xF, false); // quad_perm [1,2,3,0]
+    else
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x12F, 0xF, 0xF, false); // row_ror:15
+}
+
+// Segment of row y owned by lane j: sites [S j, S j + S) in bytes 0..S-1.
+template <int L, int LPC>
+__device__ __forceinline__ void lp_load(const uint32_t *base, size_t stride, int y, uint32_t j,
+                                        uint32_t (&seg)[PottsLP<L, LPC>::SW])
+{
+    constexpr int S = PottsLP<L, LPC>::S, SW = PottsLP<L, LPC>::SW, W = L / 4;
+    const uint32_t b0 = (uint32_t)S * j, w0 = b0 >> 2;
+    if constexpr (S % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < SW; ++k)
+            seg[k] = base[((size_t)y * W + w0 + k) * stride];
+    } else {
+        uint32_t raw[SW + 1];
+#pragma unroll
+        for (int k = 0; k <= SW; ++k) {
+            const uint32_t w = w0 + (uint32_t)k < (uint32_t)W ? w0 + (uint32_t)k : (uint32_t)W - 1u;
+            raw[k] = base[((size_t)y * W + w) * stride];
+        }
+#pragma unroll
+        for (int k = 0; k < SW; ++k)
+            seg[k] = __builtin_amdgcn_alignbyte(raw[k + 1], raw[k], b0 & 3u);
+    }
+}
+
+template <int L, int LPC>
+__device__ __forceinline__ void lp_store(uint32_t *base, size_t stride, int y, uint32_t j,
+                                         const uint32_t (&seg)[PottsLP<L, LPC>::SW])
+{
+    constexpr int S = PottsLP<L, LPC>::S, SW = PottsLP<L, LPC>::SW, W = L / 4;
+    const uint32_t b0 = (uint32_t)S * j;
+    if constexpr (S % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < SW; ++k)
+            base[((size_t)y * W + (b0 >> 2) + k) * stride] = seg[k];
+    } else {
+#pragma unroll
+        for (int m = 0; m < S; ++m) {
+            const uint32_t bb = b0 + (uint32_t)m;
+            uint8_t *p = (uint8_t *)(base + ((size_t)y * W + (bb >> 2)) * stride) + (bb & 3u);
+            *p = (uint8_t)(seg[m / 4] >> (8 * (m % 4)));
+        }
+    }
+}
+
+// Threshold-row offset and column code of a site with c = dE + 4:
+// low 8 bits the byte offset of the column in the bin's row (8 staged
+// columns in LDS, c = 8 in column 4; 9 columns in global memory), bits 8..15
+// the code c.
+template <bool TLDS>
+__device__ __forceinline__ uint32_t lp_cand(uint32_t c)
+{
+    const uint32_t col = TLDS ? ((c ^ ((c >> 1) & 4u)) & 7u) : c;
+    return (col << 2) | (c << 8);
+}
+
+// c = dE + 4 for the colours of a site: old, proposal nw, the fixed
+// neighbours (down, up, right or filler) packed with a 0xFF filler byte in
+// nb, and the left neighbour lft.
+__device__ __forceinline__ uint32_t lp_code(uint32_t nb, uint32_t old, uint32_t nw, uint32_t lft)
+{
+    const uint32_t oldrep = __builtin_amdgcn_perm(0u, old, 0u), newrep = __builtin_amdgcn_perm(0u, nw, 0u);
+    const uint32_t xo = nb ^ oldrep, xn = nb ^ newrep;
+    const uint32_t eq_old = ~(((xo & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | xo) & 0x80808080u;
+    const uint32_t ne_new = (((xn & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | xn) & 0x80808080u;
+    // the filler byte counts once as "not the new colour"; the left
+    // neighbour adds [lft == old] + [lft != nw] - 1
+    return (uint32_t)__builtin_popcount(ne_new) + (uint32_t)__builtin_popcount(eq_old) + (lft == old ? 1u : 0u) -
+           (lft == nw ? 1u : 0u);
+}
+
+template <int L, int LPC, bool TLDS, int X>
+__device__ __forceinline__ void lp_site(const uint32_t (&pr)[PottsLP<L, LPC>::S], uint32_t pl2,
+                                        const uint32_t (&ra)[PottsLP<L, LPC>::S], int32_t &rowb, int32_t &dprev,
+                                        bool &prev, uint32_t &F0, uint32_t &F1, const uint32_t *__restrict__ T)
+{
+    constexpr int S = PottsLP<L, LPC>::S;
+    constexpr int O = X / S, M = X % S;
+    uint32_t pair = group_bcast<LPC, O>(pr[M]);
+    if constexpr (X == L - 1 && L > 1) {
+        const uint32_t p2 = group_bcast<LPC, O>(pl2); // right neighbour = site 0 with its proposal
+        pair = (F0 & 1u) ? p2 : pair;
+    }
+    const uint32_t r = group_bcast<LPC, O>(ra[M]);
+    const uint32_t cand = prev ? (pair >> 16) : (pair & 0xFFFFu);
+    rowb += prev ? dprev : 0;
+    const uint32_t t = load_t<TLDS>(T, rowb + (int32_t)(cand & 0xFFu));
+    const uint32_t c = cand >> 8;
+    dprev = TLDS ? (int32_t)(c << 5) - 128 : (int32_t)c * 36 - 144;
+    const bool acc = (r < t) | (c == 4u);
+    if constexpr (X < 32)
+        F0 |= (acc ? 1u : 0u) << X;
+    else
+        F1 |= (acc ? 1u : 0u) << (X - 32);
+    prev = acc;
+}
+
+template <int L, int LPC, bool TLDS, int... X>
+__device__ __forceinline__ void lp_row(const uint32_t (&pr)[PottsLP<L, LPC>::S], uint32_t pl2,
+                                       const uint32_t (&ra)[PottsLP<L, LPC>::S], int32_t &rowb, uint32_t &F0,
+                                       uint32_t &F1, const uint32_t *__restrict__ T, std::integer_sequence<int, X...>)
+{
+    int32_t dprev = 0;
+    bool prev = false;
+    (lp_site<L, LPC, TLDS, X>(pr, pl2, ra, rowb, dprev, prev, F0, F1, T), ...);
+    rowb += prev ? dprev : 0;
+}
+
+// The sweeps of one chain (per lane: its segment), with the histogram
+// bookkeeping of sweep_block.
+template <int L, int LPC, bool TLDS>
+__device__ __forceinline__ int32_t potts_lp_sweeps(const LatticeArgs &a, uint32_t *base, size_t stride,
+                                                   uint32_t chain, uint32_t j, bool counts, int32_t b,
+                                                   const uint32_t *__restrict__ T, int32_t tbase, uint32_t *lhist,
+                                                   int hw, int flush_every)
+{
+    using P = PottsLP<L, LPC>;
+    constexpr int S = P::S, SW = P::SW, NCALL = P::NCALL, KC = L / 2; // Philox calls per row
+    const uint32_t q = (uint32_t)a.q;
+    uint32_t up[SW], cur[SW], dn[SW], nx[SW];
+    lp_load<L, LPC>(base, stride, L - 1, j, up);
+    lp_load<L, LPC>(base, stride, 0, j, cur);
+    lp_load<L, LPC>(base, stride, 1 % L, j, dn);
+    lp_load<L, LPC>(base, stride, 2 % L, j, nx);
+    int32_t rowb = TLDS ? tbase + 32 * b : 36 * b;
+    auto bin_of = [&](int32_t rb) { return TLDS ? (rb - tbase) >> 5 : rb / 36; };
+    const uint32_t first = ((uint32_t)S * j) >> 1, par = ((uint32_t)S * j) & 1u;
+    const bool lane0 = j == 0u, lanel = j == (uint32_t)(LPC - 1);
+    int until_flush = flush_every;
+    for (int s = 0; s < a.n_sweeps; ++s) {
+        const uint32_t g = a.g0 + (uint32_t)s;
+        for (int y = 0; y < L; ++y) {
+            // Philox words of the segment's sites: site i uses words
+            // 2 (i & 1) (proposal) and 2 (i & 1) + 1 (acceptance) of call i / 2
+            uint32_t w[NCALL][4];
+#pragma unroll
+            for (int k = 0; k < NCALL; ++k) {
+                const uint32_t call = first + (uint32_t)k < (uint32_t)KC ? first + (uint32_t)k : (uint32_t)KC - 1u;
+                const Words4 r = philox4x32_10(chain, g, (uint32_t)(y * KC) + call, kTagSweep, a.k0, a.k1);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    w[k][t] = r.w[t];
+            }
+            uint32_t old[S], nw[S], ra[S];
+#pragma unroll
+            for (int m = 0; m < S; ++m) {
+                uint32_t wp, wa;
+                if constexpr (S % 2 == 0) {
+                    wp = w[m / 2][2 * (m & 1)];
+                    wa = w[m / 2][2 * (m & 1) + 1];
+                } else { // the segment starts on an odd site when par = 1
+                    // a bitwise select: a conditional here becomes a dynamic
+                    // index into w (scratch)
+                    const uint32_t mk = 0u - par;
+                    wp = (w[(m + 1) / 2][2 * ((m + 1) & 1)] & mk) | (w[m / 2][2 * (m & 1)] & ~mk);
+                    wa = (w[(m + 1) / 2][2 * ((m + 1) & 1) + 1] & mk) | (w[m / 2][2 * (m & 1) + 1] & ~mk);
+                }
+                ra[m] = min(wa, 0xFFFFFFFEu); // accept iff ra < T
+                old[m] = (cur[m / 4] >> (8 * (m % 4))) & 0xFFu;
+                const uint32_t n = old[m] + 1u + __umulhi(wp, q - 1u);
+                nw[m] = min(n, n - q); // n - q wraps above n when n < q
+            }
+            // neighbours across segment ends
+            const uint32_t lh_old = group_prev<LPC>(old[S - 1]), lh_nw = group_prev<LPC>(nw[S - 1]);
+            const uint32_t rh_old = group_next<LPC>(old[0]), rh_nw = group_next<LPC>(nw[0]);
+            // the left neighbour of site 0 is site L - 1, not yet visited
+            const uint32_t l0_acc = lane0 ? lh_old : lh_nw;
+            // the right neighbour of the row's last site is site 0, visited first
+            const uint32_t rr_acc = lanel ? rh_nw : rh_old;
+            uint32_t pr[S], pl2 = 0u;
+#pragma unroll
+            for (int m = 0; m < S; ++m) {
+                // bytes: down, up (same column), right, filler
+                const uint32_t vert = __builtin_amdgcn_perm(up[m / 4], dn[m / 4],
+                                                            (uint32_t)(m % 4) | ((uint32_t)(4 + m % 4) << 8));
+                // (m is a constant of the unrolled loop: the branches fold)
+                const int mr = (m + 1) / 4 < SW ? (m + 1) / 4 : SW - 1;
+                uint32_t nb;
+                if (m + 1 < S)
+                    nb = __builtin_amdgcn_perm(vert, cur[mr],
+                                               4u | (5u << 8) | ((uint32_t)((m + 1) % 4) << 16) | (0x0Du << 24));
+                else
+                    nb = __builtin_amdgcn_perm(vert, rh_old, 4u | (5u << 8) | (0u << 16) | (0x0Du << 24));
+                const uint32_t l_rej = m > 0 ? old[m > 0 ? m - 1 : 0] : lh_old;
+                const uint32_t l_acc = m > 0 ? nw[m > 0 ? m - 1 : 0] : l0_acc;
+                pr[m] = lp_cand<TLDS>(lp_code(nb, old[m], nw[m], l_rej)) |
+                        (lp_cand<TLDS>(lp_code(nb, old[m], nw[m], l_acc)) << 16);
+                if (m + 1 == S) {
+                    const uint32_t nb2 = __builtin_amdgcn_perm(vert, rr_acc, 4u | (5u << 8) | (0x0Du << 24));
+                    pl2 = lp_cand<TLDS>(lp_code(nb2, old[m], nw[m], l_rej)) |
+                          (lp_cand<TLDS>(lp_code(nb2, old[m], nw[m], l_acc)) << 16);
+                }
+            }
+            uint32_t F0 = 0u, F1 = 0u;
+            lp_row<L, LPC, TLDS>(pr, pl2, ra, rowb, F0, F1, T, std::make_integer_sequence<int, L>{});
+            // this lane's accepted proposals: bits S j .. S j + S - 1 of F
+            const uint32_t fj = (uint32_t)((((uint64_t)F1 << 32) | F0) >> (S * j));
+#pragma unroll
+            for (int m = 0; m < S; ++m)
+                cur[m / 4] ^= ((fj >> m) & 1u) ? (old[m] ^ nw[m]) << (8 * (m % 4)) : 0u;
+            lp_store<L, LPC>(base, stride, y, j, cur);
+#pragma unroll
+            for (int k = 0; k < SW; ++k) {
+                up[k] = cur[k];
+                cur[k] = dn[k];
+                dn[k] = nx[k];
+            }
+            lp_load<L, LPC>(base, stride, (y + 3) % L, j, nx);
+        }
+        if (counts) {
+            const int32_t bb = bin_of(rowb);
+            atomicAdd(&lhist[bb >> 1], 1u << ((bb & 1) << 4));
+        }
+        if (--until_flush == 0 && s + 1 < a.n_sweeps) {
+            until_flush = flush_every;
+            __syncthreads();
+            flush_hist(lhist, hw, a.hist);
+            __syncthreads();
+        }
+    }
+    return bin_of(rowb);
+}
+
+// ---------------------------------------------------------------------------
+// One block of chains: threads [0, blockDim) handle chains
+// [c_first, c_first + blockDim / LPC) of the instance described by `a`.
+// The threshold table is staged into LDS (TLDS) and the block's histogram is
+// accumulated in LDS, then added to the instance's global histogram.
+// Used by the plain kernel (one launch per instance) and by the persistent
+// batched kernel (one block per work item).
+// ---------------------------------------------------------------------------
 template <int MODEL, int L, int LAYOUT, bool TLDS, int LPC>
 __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, uint32_t *smem)
 {
@@ -427,7 +702,12 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
     const int flush_every = kMaxBlockCount / (int)(blockDim.x / LPC);
     int until_flush = flush_every;
 
-    if constexpr (MODEL == kPotts) {
+    if constexpr (MODEL == kPotts && PottsLP<L, LPC>::ok) {
+        int32_t tbase = 0;
+        if constexpr (TLDS)
+            tbase = (int32_t)(uint32_t)(uintptr_t)(lds_u32 *)smem;
+        b = potts_lp_sweeps<L, LPC, TLDS>(a, base, stride, chain, j, counts, b, T, tbase, lhist, hw, flush_every);
+    } else if constexpr (MODEL == kPotts) {
         constexpr int W = Geom<L, LAYOUT>::kWpr;
         const uint32_t q = (uint32_t)a.q;
         uint32_t up[W], cur[W], dn[W], nx[W];

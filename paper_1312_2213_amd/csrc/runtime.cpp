@@ -107,8 +107,10 @@ int muca_geometry(const muca_config *c, Geometry *g)
     g->wpr = words_per_row(c->L, g->layout);
     int lpc = c->lanes_per_chain;
     if (lpc == 0) {
-        // enough lanes to give every SIMD of the chip a wavefront, at most 16
-        lpc = 16;
+        // enough lanes to give every SIMD of the chip a wavefront, at most 16;
+        // Potts splits each row over the lanes (L / lpc sites per lane), so
+        // 16 lanes need L a multiple of 16
+        lpc = (c->model == kPotts && c->L % 16) ? 4 : 16;
         while (lpc > 1 && (long)g->c_pad * lpc > 65536L)
             lpc /= lpc == 16 ? 4 : 2;
     }
