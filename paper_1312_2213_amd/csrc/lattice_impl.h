@@ -505,24 +505,53 @@ __device__ __forceinline__ uint32_t lp_code(uint32_t nb, uint32_t old, uint32_t 
            (lft == nw ? 1u : 0u);
 }
 
-template <int L, int LPC, bool TLDS, int X>
-__device__ __forceinline__ void lp_site(const uint32_t (&pr)[PottsLP<L, LPC>::S], uint32_t pl2,
-                                        const uint32_t (&ra)[PottsLP<L, LPC>::S], int32_t &rowb, int32_t &dprev,
-                                        bool &prev, uint32_t &F0, uint32_t &F1, const uint32_t *__restrict__ T)
+// Descriptor pair of site X (rejected / accepted left neighbour), from the
+// owning lane; the row's last site uses the variant for site 0's outcome.
+template <int L, int LPC, int X>
+__device__ __forceinline__ uint32_t lp_pair(const uint32_t (&pr)[PottsLP<L, LPC>::S], uint32_t pl2, uint32_t F0)
 {
     constexpr int S = PottsLP<L, LPC>::S;
-    constexpr int O = X / S, M = X % S;
-    uint32_t pair = group_bcast<LPC, O>(pr[M]);
+    uint32_t pair = group_bcast<LPC, X / S>(pr[X % S]);
     if constexpr (X == L - 1 && L > 1) {
-        const uint32_t p2 = group_bcast<LPC, O>(pl2); // right neighbour = site 0 with its proposal
+        const uint32_t p2 = group_bcast<LPC, X / S>(pl2);
         pair = (F0 & 1u) ? p2 : pair;
     }
-    const uint32_t r = group_bcast<LPC, O>(ra[M]);
-    const uint32_t cand = prev ? (pair >> 16) : (pair & 0xFFFFu);
-    rowb += prev ? dprev : 0;
-    const uint32_t t = load_t<TLDS>(T, rowb + (int32_t)(cand & 0xFFu));
-    const uint32_t c = cand >> 8;
-    dprev = TLDS ? (int32_t)(c << 5) - 128 : (int32_t)c * 36 - 144;
+    return pair;
+}
+
+// Site X.  Its two candidate thresholds (t0: previous site rejected, t1:
+// accepted) and codes were read during the previous site; `rowb` and `dstep`
+// are those of the previous site's attempt.  Before this site's compare, the
+// next site's two candidate thresholds are read, so each LDS read has a whole
+// site to complete and the loop-carried chain is select -> compare.
+template <int L, int LPC, bool TLDS, int X>
+__device__ __forceinline__ void lp_site(const uint32_t (&pr)[PottsLP<L, LPC>::S], uint32_t pl2,
+                                        const uint32_t (&ra)[PottsLP<L, LPC>::S], int32_t &rowb, int32_t &dstep,
+                                        bool &prev, uint32_t &t0, uint32_t &t1, uint32_t &c0, uint32_t &c1,
+                                        uint32_t &F0, uint32_t &F1, const uint32_t *__restrict__ T)
+{
+    constexpr int S = PottsLP<L, LPC>::S;
+    rowb += prev ? dstep : 0; // the row of this site's attempt
+    const uint32_t c = prev ? c1 : c0;
+    dstep = TLDS ? (int32_t)(c << 5) - 128 : (int32_t)c * 36 - 144;
+    const uint32_t r = group_bcast<LPC, X / S>(ra[X % S]);
+    uint32_t n_t0 = 0u, n_t1 = 0u, n_c0 = 0u, n_c1 = 0u;
+    if constexpr (X + 1 < L) {
+        const uint32_t pair = lp_pair<L, LPC, X + 1>(pr, pl2, F0);
+        n_t0 = load_t<TLDS>(T, rowb + (int32_t)(pair & 0xFFu));
+        n_t1 = load_t<TLDS>(T, rowb + dstep + (int32_t)((pair >> 16) & 0xFFu));
+        n_c0 = (pair >> 8) & 0xFFu;
+        n_c1 = pair >> 24;
+    }
+    // selected only now, after the next reads were issued; the scheduling
+    // barrier keeps the compiler from pulling this select (and its wait for
+    // the reads) up against the reads just issued
+    __builtin_amdgcn_sched_barrier(0);
+    const uint32_t t = prev ? t1 : t0;
+    t0 = n_t0;
+    t1 = n_t1;
+    c0 = n_c0;
+    c1 = n_c1;
     const bool acc = (r < t) | (c == 4u);
     if constexpr (X < 32)
         F0 |= (acc ? 1u : 0u) << X;
@@ -536,10 +565,14 @@ __device__ __forceinline__ void lp_row(const uint32_t (&pr)[PottsLP<L, LPC>::S],
                                        const uint32_t (&ra)[PottsLP<L, LPC>::S], int32_t &rowb, uint32_t &F0,
                                        uint32_t &F1, const uint32_t *__restrict__ T, std::integer_sequence<int, X...>)
 {
-    int32_t dprev = 0;
+    // site 0: the left neighbour (site L - 1) is not yet visited, one candidate
+    const uint32_t p0 = lp_pair<L, LPC, 0>(pr, pl2, 0u);
+    uint32_t t0 = load_t<TLDS>(T, rowb + (int32_t)(p0 & 0xFFu)), t1 = t0;
+    uint32_t c0 = (p0 >> 8) & 0xFFu, c1 = c0;
+    int32_t dstep = 0;
     bool prev = false;
-    (lp_site<L, LPC, TLDS, X>(pr, pl2, ra, rowb, dprev, prev, F0, F1, T), ...);
-    rowb += prev ? dprev : 0;
+    (lp_site<L, LPC, TLDS, X>(pr, pl2, ra, rowb, dstep, prev, t0, t1, c0, c1, F0, F1, T), ...);
+    rowb += prev ? dstep : 0;
 }
 
 // The sweeps of one chain (per lane: its segment), with the histogram
