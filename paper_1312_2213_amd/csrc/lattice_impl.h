@@ -105,6 +105,35 @@ struct RowRng {
     }
 };
 
+// value of lane O of the chain's lane group
+template <int LPC, int O>
+__device__ __forceinline__ uint32_t group_bcast(uint32_t v)
+{
+    if constexpr (LPC == 4)
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, O * 0x55, 0xF, 0xF, false);
+    else
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x150 + O, 0xF, 0xF, false);
+}
+
+// value of the previous / next lane of the group, cyclic
+template <int LPC>
+__device__ __forceinline__ uint32_t group_prev(uint32_t v)
+{
+    if constexpr (LPC == 4)
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x93, 0xF, 0xF, false); // quad_perm [3,0,1,2]
+    else
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x121, 0xF, 0xF, false); // row_ror:1
+}
+
+template <int LPC>
+__device__ __forceinline__ uint32_t group_next(uint32_t v)
+{
+    if constexpr (LPC == 4)
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x39, 0xF, 0xF, false); // quad_perm [1,2,3,0]
+    else
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x12F, 0xF, 0xF, false); // row_ror:15
+}
+
 // ---------------------------------------------------------------------------
 // Ising / MUMA.  Rows are held bit-packed in registers whatever the storage
 // layout (bit 1 = spin +1, W1 = ceil(L/32) words, unused high bits zero).
@@ -256,6 +285,157 @@ __device__ __forceinline__ void ising_row(const uint32_t (&up)[Row1<L>::W], uint
      ...);
 }
 
+// ---------------------------------------------------------------------------
+// Ising / MUMA with the per-site candidate work split over the lanes of a
+// chain (4 or 16 lanes).  The lane that draws a site's Philox word (site X:
+// call X / 4, lane (X / 4) % LPC) computes, from bit planes of the row as it
+// was when the row started, the threshold offset and bin step of the site
+// for both outcomes of the left neighbour's attempt; the row's last site,
+// whose right neighbour is site 0, keeps both variants of that too.  The
+// row's attempts then run on all lanes with one DPP broadcast of the site's
+// descriptor, both candidate thresholds of the next site being read before
+// the current compare.
+// ---------------------------------------------------------------------------
+// one candidate: the threshold's byte offset from the bin's row origin and
+// the origin's shift on acceptance, signed bytes
+template <int MODEL>
+__device__ __forceinline__ uint32_t ilp_cand(int32_t nmis4, uint32_t plus)
+{
+    const int32_t off = col_addr<MODEL>(0, nmis4, plus);
+    const int32_t ds = bin_step<MODEL>(nmis4, plus);
+    return ((uint32_t)off & 0xFFu) | (((uint32_t)ds & 0xFFu) << 8);
+}
+
+__device__ __forceinline__ int32_t sbyte(uint32_t v) { return (int32_t)(int8_t)(uint8_t)v; }
+
+template <int L, int LPC, int X>
+__device__ __forceinline__ uint32_t ilp_pair(const uint32_t (&desc)[RowRng<L, LPC, 1>::kPerLane * 4], uint32_t dlast,
+                                             uint32_t F0)
+{
+    constexpr int call = X / 4, O = call % LPC, R = (call / LPC) * 4 + X % 4;
+    uint32_t pair = group_bcast<LPC, O>(desc[R]);
+    if constexpr (X == L - 1 && L > 1) {
+        const uint32_t p2 = group_bcast<LPC, O>(dlast); // site 0 flipped
+        pair = (F0 & 1u) ? p2 : pair;
+    }
+    return pair;
+}
+
+template <int MODEL, int L, int LPC, bool TLDS, int X>
+__device__ __forceinline__ void ilp_site(const uint32_t (&desc)[RowRng<L, LPC, 1>::kPerLane * 4], uint32_t dlast,
+                                         const RowRng<L, LPC, 1> &rng, int32_t &rowb, int32_t &dstep, bool &prev,
+                                         uint32_t &t0, uint32_t &t1, uint32_t &c0, uint32_t &c1,
+                                         uint32_t (&F)[Row1<L>::W], const uint32_t *__restrict__ T)
+{
+    rowb += prev ? dstep : 0; // the bin row of this site's attempt
+    const uint32_t cand = prev ? c1 : c0;
+    dstep = sbyte(cand >> 8);
+    const uint32_t r = rng.template get<X, 0>(); // clamped: accept iff r < T
+    uint32_t n_t0 = 0u, n_t1 = 0u, n_c0 = 0u, n_c1 = 0u;
+    if constexpr (X + 1 < L) {
+        const uint32_t pair = ilp_pair<L, LPC, X + 1>(desc, dlast, F[0]);
+        n_t0 = load_t<TLDS>(T, rowb + sbyte(pair));
+        n_t1 = load_t<TLDS>(T, rowb + dstep + sbyte(pair >> 16));
+        n_c0 = pair & 0xFFFFu;
+        n_c1 = pair >> 16;
+    }
+    // selected only now, after the next reads were issued (the barrier keeps
+    // the wait for this site's reads one site behind them)
+    __builtin_amdgcn_sched_barrier(0);
+    const uint32_t t = prev ? t1 : t0;
+    t0 = n_t0;
+    t1 = n_t1;
+    c0 = n_c0;
+    c1 = n_c1;
+    const bool acc = r < t;
+    F[X / 32] |= (acc ? 1u : 0u) << (X % 32);
+    prev = acc;
+}
+
+template <int MODEL, int L, int LPC, bool TLDS, int... X>
+__device__ __forceinline__ void ilp_sites(const uint32_t (&desc)[RowRng<L, LPC, 1>::kPerLane * 4], uint32_t dlast,
+                                          const RowRng<L, LPC, 1> &rng, int32_t &rowb, uint32_t (&F)[Row1<L>::W],
+                                          const uint32_t *__restrict__ T, std::integer_sequence<int, X...>)
+{
+    const uint32_t p0 = ilp_pair<L, LPC, 0>(desc, dlast, 0u); // site 0: one candidate
+    uint32_t t0 = load_t<TLDS>(T, rowb + sbyte(p0)), t1 = t0;
+    uint32_t c0 = p0 & 0xFFFFu, c1 = c0;
+    int32_t dstep = 0;
+    bool prev = false;
+    (ilp_site<MODEL, L, LPC, TLDS, X>(desc, dlast, rng, rowb, dstep, prev, t0, t1, c0, c1, F, T), ...);
+    rowb += prev ? dstep : 0;
+}
+
+template <int MODEL, int L, int LPC, bool TLDS>
+__device__ __forceinline__ void ising_lp_row(const uint32_t (&up)[Row1<L>::W], uint32_t (&cur)[Row1<L>::W],
+                                             const uint32_t (&dn)[Row1<L>::W], int32_t &rowb,
+                                             const uint32_t *__restrict__ T, uint32_t chain, uint32_t g, int y,
+                                             uint32_t j, uint32_t k0, uint32_t k1)
+{
+    constexpr int W = Row1<L>::W;
+    using R = RowRng<L, LPC, 1>;
+    R rng;
+    rng.fill(chain, g, y, j, k0, k1);
+    // bit planes of the row as it started: misalignment with the right, up
+    // and down neighbours (parity s0, majority s1), with the right one alone
+    // (MR) and with the left one (ML); the spins themselves (S)
+    uint32_t s0[W], s1[W], MR[W], ML[W];
+#pragma unroll
+    for (int wi = 0; wi < W; ++wi) {
+        const int nb = (L - 32 * wi) < 32 ? (L - 32 * wi) : 32;
+        const uint32_t S = cur[wi];
+        const uint32_t nextbit = (wi + 1 < W) ? (cur[wi + 1 < W ? wi + 1 : 0] & 1u) : (cur[0] & 1u);
+        const uint32_t prevbit = (wi > 0) ? (cur[wi > 0 ? wi - 1 : 0] >> 31) : ((cur[W - 1] >> ((L - 1) % 32)) & 1u);
+        const uint32_t Rn = (S >> 1) | (nextbit << (nb - 1));
+        const uint32_t Ln = (S << 1) | prevbit;
+        const uint32_t mr = S ^ Rn, mu = S ^ up[wi], md = S ^ dn[wi];
+        MR[wi] = mr;
+        ML[wi] = S ^ Ln;
+        s0[wi] = mr ^ mu ^ md;
+        s1[wi] = (mr & mu) | (mr & md) | (mu & md);
+    }
+    // this lane's sites: those of its Philox calls
+    uint32_t desc[R::kPerLane * 4], dlast = 0u;
+#pragma unroll
+    for (int m = 0; m < R::kPerLane; ++m) {
+        uint32_t call = j + (uint32_t)(LPC * m);
+        if (R::kCalls % LPC)
+            call = call < (uint32_t)R::kCalls ? call : (uint32_t)R::kCalls - 1u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t x = 4u * call + (uint32_t)k, wi = x >> 5, bit = x & 31u;
+            uint32_t ps0 = s0[0], ps1 = s1[0], pml = ML[0], pmr = MR[0], ps = cur[0];
+            if constexpr (W == 2) {
+                ps0 = wi ? s0[W - 1] : ps0;
+                ps1 = wi ? s1[W - 1] : ps1;
+                pml = wi ? ML[W - 1] : pml;
+                pmr = wi ? MR[W - 1] : pmr;
+                ps = wi ? cur[W - 1] : ps;
+            }
+            const uint32_t cnt = ((ps1 >> bit) & 1u) * 2u + ((ps0 >> bit) & 1u); // misaligned of right, up, down
+            const uint32_t ml = (pml >> bit) & 1u, plus = (ps >> bit) & 1u;
+            const int32_t n0 = (int32_t)(4u * (cnt + ml));
+            // site 0's left neighbour (site L - 1) is not yet visited: no flip
+            const int32_t n1 = x == 0u ? n0 : (int32_t)(4u * (cnt + (ml ^ 1u)));
+            desc[4 * m + k] = ilp_cand<MODEL>(n0, plus) | (ilp_cand<MODEL>(n1, plus) << 16);
+            if (m == (R::kCalls - 1) / LPC && k == 3) {
+                // the row's last site with site 0 flipped: its right neighbour toggles
+                const uint32_t cnt2 = ((pmr >> bit) & 1u) ? cnt - 1u : cnt + 1u;
+                dlast = ilp_cand<MODEL>((int32_t)(4u * (cnt2 + ml)), plus) |
+                        (ilp_cand<MODEL>((int32_t)(4u * (cnt2 + (ml ^ 1u))), plus) << 16);
+            }
+        }
+    }
+    uint32_t F[W];
+#pragma unroll
+    for (int wi = 0; wi < W; ++wi)
+        F[wi] = 0u;
+    ilp_sites<MODEL, L, LPC, TLDS>(desc, dlast, rng, rowb, F, T, std::make_integer_sequence<int, L>{});
+#pragma unroll
+    for (int wi = 0; wi < W; ++wi)
+        cur[wi] ^= F[wi];
+}
+
 // Storage <-> packed row.  BYTE storage holds int8 +1 (0x01) / -1 (0xFF),
 // four sites per word; bit 1 of a byte is set exactly for -1.
 template <int L, int LAYOUT>
@@ -405,35 +585,6 @@ struct PottsLP {
     static constexpr int SW = (S + 3) / 4;  // words of a lane's segment
     static constexpr int NCALL = S / 2 + 1; // Philox calls that cover S sites from any first site
 };
-
-// value of lane O of the chain's lane group
-template <int LPC, int O>
-__device__ __forceinline__ uint32_t group_bcast(uint32_t v)
-{
-    if constexpr (LPC == 4)
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, O * 0x55, 0xF, 0xF, false);
-    else
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x150 + O, 0xF, 0xF, false);
-}
-
-// value of the previous / next lane of the group, cyclic
-template <int LPC>
-__device__ __forceinline__ uint32_t group_prev(uint32_t v)
-{
-    if constexpr (LPC == 4)
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x93, 0xF, 0xF, false); // quad_perm [3,0,1,2]
-    else
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x121, 0xF, 0xF, false); // row_ror:1
-}
-
-template <int LPC>
-__device__ __forceinline__ uint32_t group_next(uint32_t v)
-{
-    if constexpr (LPC == 4)
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x39, 0xF, 0xF, false); // quad_perm [1,2,3,0]
-    else
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x12F, 0xF, 0xF, false); // row_ror:15
-}
 
 // Segment of row y owned by lane j: sites [S j, S j + S) in bytes 0..S-1.
 template <int L, int LPC>
@@ -805,8 +956,11 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
         for (int s = 0; s < a.n_sweeps; ++s) {
             const uint32_t g = a.g0 + (uint32_t)s;
             for (int y = 0; y < L; ++y) {
-                ising_row<MODEL, L, LPC, TLDS>(up, cur, dn, rowb, T, chain, g, y, j, a.k0, a.k1,
-                                               std::make_integer_sequence<int, W>{});
+                if constexpr (LPC >= 4)
+                    ising_lp_row<MODEL, L, LPC, TLDS>(up, cur, dn, rowb, T, chain, g, y, j, a.k0, a.k1);
+                else
+                    ising_row<MODEL, L, LPC, TLDS>(up, cur, dn, rowb, T, chain, g, y, j, a.k0, a.k1,
+                                                   std::make_integer_sequence<int, W>{});
                 if (leader)
                     store_row<L, LAYOUT>(base, stride, y, cur);
 #pragma unroll
