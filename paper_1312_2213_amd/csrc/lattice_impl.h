@@ -288,56 +288,99 @@ __device__ __forceinline__ void ising_row(const uint32_t (&up)[Row1<L>::W], uint
 // ---------------------------------------------------------------------------
 // Ising / MUMA with the per-site candidate work split over the lanes of a
 // chain (4 or 16 lanes).  The lane that draws a site's Philox word (site X:
-// call X / 4, lane (X / 4) % LPC) computes, from bit planes of the row as it
-// was when the row started, the threshold offset and bin step of the site
-// for both outcomes of the left neighbour's attempt; the row's last site,
-// whose right neighbour is site 0, keeps both variants of that too.  The
-// row's attempts then run on all lanes with one DPP broadcast of the site's
-// descriptor, both candidate thresholds of the next site being read before
-// the current compare.
+// call X / 4, lane (X / 4) % LPC) also builds, from bit planes of the row as
+// it was when the row started, the site's descriptor: for both outcomes of
+// the left neighbour's attempt, the site's bin step, and the next site's
+// threshold offset for both outcomes of this site's own attempt (signed
+// bytes).  The right, up and down neighbours of a site do not change before
+// its attempt, except for the row's last site, whose right neighbour is site
+// 0: the descriptors that involve it (sites L - 2 and L - 1) have a second
+// variant for site 0 flipped.  The descriptor travels with the site's
+// acceptance word in one 64-bit DPP broadcast, so a site costs: two selects
+// of the bin rows (this site's and, if it flips, the next site's), two
+// addresses and two reads of the next site's candidate thresholds, one
+// broadcast, and select + compare of its own threshold, read one site
+// earlier.
 // ---------------------------------------------------------------------------
-// one candidate: the threshold's byte offset from the bin's row origin and
-// the origin's shift on acceptance, signed bytes
-template <int MODEL>
-__device__ __forceinline__ uint32_t ilp_cand(int32_t nmis4, uint32_t plus)
-{
-    const int32_t off = col_addr<MODEL>(0, nmis4, plus);
-    const int32_t ds = bin_step<MODEL>(nmis4, plus);
-    return ((uint32_t)off & 0xFFu) | (((uint32_t)ds & 0xFFu) << 8);
-}
-
 __device__ __forceinline__ int32_t sbyte(uint32_t v) { return (int32_t)(int8_t)(uint8_t)v; }
 
-template <int L, int LPC, int X>
-__device__ __forceinline__ uint32_t ilp_pair(const uint32_t (&desc)[RowRng<L, LPC, 1>::kPerLane * 4], uint32_t dlast,
-                                             uint32_t F0)
+// value of lane O of the chain's lane group, 64 bits (one v_mov_b64 DPP with
+// row_newbcast; two 32-bit quad permutes for groups of 4)
+template <int LPC, int O>
+__device__ __forceinline__ uint64_t group_bcast64(uint64_t v)
 {
-    constexpr int call = X / 4, O = call % LPC, R = (call / LPC) * 4 + X % 4;
-    uint32_t pair = group_bcast<LPC, O>(desc[R]);
-    if constexpr (X == L - 1 && L > 1) {
-        const uint32_t p2 = group_bcast<LPC, O>(dlast); // site 0 flipped
-        pair = (F0 & 1u) ? p2 : pair;
-    }
-    return pair;
+    if constexpr (LPC == 16)
+        return __builtin_amdgcn_mov_dpp(v, 0x150 + O, 0xF, 0xF, false);
+    else
+        return (uint64_t)group_bcast<LPC, O>((uint32_t)v) | ((uint64_t)group_bcast<LPC, O>((uint32_t)(v >> 32)) << 32);
 }
 
-template <int MODEL, int L, int LPC, bool TLDS, int X>
-__device__ __forceinline__ void ilp_site(const uint32_t (&desc)[RowRng<L, LPC, 1>::kPerLane * 4], uint32_t dlast,
-                                         const RowRng<L, LPC, 1> &rng, int32_t &rowb, int32_t &dstep, bool &prev,
-                                         uint32_t &t0, uint32_t &t1, uint32_t &c0, uint32_t &c1,
-                                         uint32_t (&F)[Row1<L>::W], const uint32_t *__restrict__ T)
+// two signed bytes: f(nA) | f(nB) << 8, for the site's misalignment count
+// without (nA) and with (nB) the left neighbour's flip
+template <int MODEL>
+__device__ __forceinline__ uint32_t ilp_off2(uint32_t nA, uint32_t nB, uint32_t plus)
 {
-    rowb += prev ? dstep : 0; // the bin row of this site's attempt
-    const uint32_t cand = prev ? c1 : c0;
-    dstep = sbyte(cand >> 8);
-    const uint32_t r = rng.template get<X, 0>(); // clamped: accept iff r < T
-    uint32_t n_t0 = 0u, n_t1 = 0u, n_c0 = 0u, n_c1 = 0u;
+    const int32_t a = col_addr<MODEL>(0, (int32_t)(4u * nA), plus), b = col_addr<MODEL>(0, (int32_t)(4u * nB), plus);
+    return ((uint32_t)a & 0xFFu) | (((uint32_t)b & 0xFFu) << 8);
+}
+
+template <int MODEL>
+__device__ __forceinline__ uint32_t ilp_ds2(uint32_t nA, uint32_t nB, uint32_t plus)
+{
+    const int32_t a = bin_step<MODEL>((int32_t)(4u * nA), plus), b = bin_step<MODEL>((int32_t)(4u * nB), plus);
+    return ((uint32_t)a & 0xFFu) | (((uint32_t)b & 0xFFu) << 8);
+}
+
+// (v << 1) | (this lane's bit of mask): one add with carry-in.  The mask is
+// the lane mask written by a vector compare; inside the site loop that
+// compare is a scheduling region (four or more instructions) back, after the
+// loop it may be the previous instruction, hence there the two wait states
+// of an SGPR written by one VALU instruction and read by the next.
+template <bool NEAR>
+__device__ __forceinline__ uint32_t shift_in(uint32_t v, uint64_t mask)
+{
+    uint32_t out;
+    if constexpr (NEAR)
+        asm("s_nop 1\n\tv_addc_co_u32 %0, vcc, %1, %1, %2" : "=v"(out) : "v"(v), "s"(mask) : "vcc");
+    else
+        asm("v_addc_co_u32 %0, vcc, %1, %1, %2" : "=v"(out) : "v"(v), "s"(mask) : "vcc");
+    return out;
+}
+
+// (descriptor, acceptance word) of site X as every lane of the chain sees it
+template <int L, int LPC, int X>
+__device__ __forceinline__ uint64_t ilp_get(const uint64_t (&pk)[RowRng<L, LPC, 1>::kPerLane * 4], uint32_t dv2,
+                                            uint32_t dv1, bool f0)
+{
+    constexpr int call = X / 4, O = call % LPC, R = (call / LPC) * 4 + X % 4;
+    uint64_t v = group_bcast64<LPC, O>(pk[R]);
+    if constexpr (X == L - 2 || X == L - 1) {
+        const uint32_t alt = group_bcast<LPC, O>(X == L - 2 ? dv2 : dv1); // site 0 flipped
+        v = f0 ? ((v & 0xFFFFFFFF00000000ull) | alt) : v;
+    }
+    return v;
+}
+
+// Site X.  On entry: B = bin row (byte origin) before the site's attempt if
+// the previous site was rejected, Bf = the same if it was accepted, prev =
+// that outcome, (t0, t1) = the site's threshold in either case (read one
+// site earlier), cur = the site's (descriptor, word).
+template <int MODEL, int L, int LPC, bool TLDS, int X>
+__device__ __forceinline__ void ilp_site(const uint64_t (&pk)[RowRng<L, LPC, 1>::kPerLane * 4], uint32_t dv2,
+                                         uint32_t dv1, int32_t &B, int32_t &Bf, uint64_t &cur, bool &prev, bool &f0,
+                                         uint64_t &pm, uint32_t &t0, uint32_t &t1, uint32_t (&F)[Row1<L>::W],
+                                         const uint32_t *__restrict__ T)
+{
+    const uint32_t D = (uint32_t)cur, r = (uint32_t)(cur >> 32); // r clamped: accept iff r < T
+    const int32_t x0 = B + sbyte(D >> 16), x1 = Bf + sbyte(D >> 24);
+    B = prev ? Bf : B;   // this site's bin row
+    Bf = prev ? x1 : x0; // the next site's, if this one flips
+    uint32_t n_t0 = 0u, n_t1 = 0u;
+    uint64_t nxt = 0u;
     if constexpr (X + 1 < L) {
-        const uint32_t pair = ilp_pair<L, LPC, X + 1>(desc, dlast, F[0]);
-        n_t0 = load_t<TLDS>(T, rowb + sbyte(pair));
-        n_t1 = load_t<TLDS>(T, rowb + dstep + sbyte(pair >> 16));
-        n_c0 = pair & 0xFFFFu;
-        n_c1 = pair >> 16;
+        n_t0 = load_t<TLDS>(T, B + sbyte(D));
+        n_t1 = load_t<TLDS>(T, Bf + sbyte(D >> 8));
+        nxt = ilp_get<L, LPC, X + 1>(pk, dv2, dv1, f0);
     }
     // selected only now, after the next reads were issued (the barrier keeps
     // the wait for this site's reads one site behind them)
@@ -345,25 +388,30 @@ __device__ __forceinline__ void ilp_site(const uint32_t (&desc)[RowRng<L, LPC, 1
     const uint32_t t = prev ? t1 : t0;
     t0 = n_t0;
     t1 = n_t1;
-    c0 = n_c0;
-    c1 = n_c1;
+    cur = nxt;
+    if constexpr (X > 0)
+        F[(X - 1) / 32] = shift_in<false>(F[(X - 1) / 32], pm);
     const bool acc = r < t;
-    F[X / 32] |= (acc ? 1u : 0u) << (X % 32);
+    if constexpr (X == 0)
+        f0 = acc;
+    pm = __builtin_amdgcn_ballot_w64(acc);
     prev = acc;
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 template <int MODEL, int L, int LPC, bool TLDS, int... X>
-__device__ __forceinline__ void ilp_sites(const uint32_t (&desc)[RowRng<L, LPC, 1>::kPerLane * 4], uint32_t dlast,
-                                          const RowRng<L, LPC, 1> &rng, int32_t &rowb, uint32_t (&F)[Row1<L>::W],
+__device__ __forceinline__ void ilp_sites(const uint64_t (&pk)[RowRng<L, LPC, 1>::kPerLane * 4], uint32_t dv2,
+                                          uint32_t dv1, uint32_t first, int32_t &rowb, uint32_t (&F)[Row1<L>::W],
                                           const uint32_t *__restrict__ T, std::integer_sequence<int, X...>)
 {
-    const uint32_t p0 = ilp_pair<L, LPC, 0>(desc, dlast, 0u); // site 0: one candidate
-    uint32_t t0 = load_t<TLDS>(T, rowb + sbyte(p0)), t1 = t0;
-    uint32_t c0 = p0 & 0xFFFFu, c1 = c0;
-    int32_t dstep = 0;
-    bool prev = false;
-    (ilp_site<MODEL, L, LPC, TLDS, X>(desc, dlast, rng, rowb, dstep, prev, t0, t1, c0, c1, F, T), ...);
-    rowb += prev ? dstep : 0;
+    uint64_t cur = ilp_get<L, LPC, 0>(pk, dv2, dv1, false);
+    uint32_t t0 = load_t<TLDS>(T, rowb + sbyte(group_bcast<LPC, 0>(first))), t1 = t0;
+    int32_t B = rowb, Bf = rowb;
+    bool prev = false, f0 = false;
+    uint64_t pm = 0u;
+    (ilp_site<MODEL, L, LPC, TLDS, X>(pk, dv2, dv1, B, Bf, cur, prev, f0, pm, t0, t1, F, T), ...);
+    F[(L - 1) / 32] = shift_in<true>(F[(L - 1) / 32], pm);
+    rowb = prev ? Bf : B;
 }
 
 template <int MODEL, int L, int LPC, bool TLDS>
@@ -372,6 +420,7 @@ __device__ __forceinline__ void ising_lp_row(const uint32_t (&up)[Row1<L>::W], u
                                              const uint32_t *__restrict__ T, uint32_t chain, uint32_t g, int y,
                                              uint32_t j, uint32_t k0, uint32_t k1)
 {
+    static_assert(L % 4 == 0 && L >= 4, "rows of whole Philox calls");
     constexpr int W = Row1<L>::W;
     using R = RowRng<L, LPC, 1>;
     R rng;
@@ -394,46 +443,68 @@ __device__ __forceinline__ void ising_lp_row(const uint32_t (&up)[Row1<L>::W], u
         s0[wi] = mr ^ mu ^ md;
         s1[wi] = (mr & mu) | (mr & md) | (mu & md);
     }
-    // this lane's sites: those of its Philox calls
-    uint32_t desc[R::kPerLane * 4], dlast = 0u;
+    // the five sites 4 call .. 4 call + 4 of each of this lane's calls: a
+    // window of every plane starting at the call's first site
+    auto window = [&](const uint32_t (&P)[W], uint32_t call) -> uint32_t {
+        if constexpr (W == 1)
+            return P[0] >> (4u * call);
+        else
+            return (uint32_t)((((uint64_t)P[1] << 32) | P[0]) >> (4u * call));
+    };
+    uint64_t pk[R::kPerLane * 4];
+    uint32_t dv2 = 0u, dv1 = 0u, first = 0u;
 #pragma unroll
     for (int m = 0; m < R::kPerLane; ++m) {
         uint32_t call = j + (uint32_t)(LPC * m);
         if (R::kCalls % LPC)
             call = call < (uint32_t)R::kCalls ? call : (uint32_t)R::kCalls - 1u;
+        const uint32_t w0 = window(s0, call), w1 = window(s1, call), wl = window(ML, call), wr = window(MR, call),
+                       ws = window(cur, call);
+        const bool last = call == (uint32_t)R::kCalls - 1u;
+        // per site k of the window: both offsets (Hoff) and both bin steps (Hds)
+        uint32_t hoff[5], hds[4], hoffv = 0u, hdsv = 0u;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const uint32_t cnt = ((w1 >> k) & 1u) * 2u + ((w0 >> k) & 1u); // misaligned of right, up, down
+            const uint32_t ml = (wl >> k) & 1u, plus = (ws >> k) & 1u;
+            const uint32_t nA = cnt + ml;
+            // site 0's left neighbour (site L - 1) is not yet visited: no flip
+            const uint32_t nB = (k == 0 && call == 0u) ? nA : cnt + (ml ^ 1u);
+            hoff[k] = ilp_off2<MODEL>(nA, nB, plus);
+            if (k < 4)
+                hds[k] = ilp_ds2<MODEL>(nA, nB, plus);
+            if (k == 3) {
+                // the last site with site 0 flipped: its right neighbour toggles
+                const uint32_t c2 = ((wr >> k) & 1u) ? cnt - 1u : cnt + 1u;
+                hoffv = ilp_off2<MODEL>(c2 + ml, c2 + (ml ^ 1u), plus);
+                hdsv = ilp_ds2<MODEL>(c2 + ml, c2 + (ml ^ 1u), plus);
+            }
+        }
+        if (m == 0)
+            first = hoff[0];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const uint32_t x = 4u * call + (uint32_t)k, wi = x >> 5, bit = x & 31u;
-            uint32_t ps0 = s0[0], ps1 = s1[0], pml = ML[0], pmr = MR[0], ps = cur[0];
-            if constexpr (W == 2) {
-                ps0 = wi ? s0[W - 1] : ps0;
-                ps1 = wi ? s1[W - 1] : ps1;
-                pml = wi ? ML[W - 1] : pml;
-                pmr = wi ? MR[W - 1] : pmr;
-                ps = wi ? cur[W - 1] : ps;
-            }
-            const uint32_t cnt = ((ps1 >> bit) & 1u) * 2u + ((ps0 >> bit) & 1u); // misaligned of right, up, down
-            const uint32_t ml = (pml >> bit) & 1u, plus = (ps >> bit) & 1u;
-            const int32_t n0 = (int32_t)(4u * (cnt + ml));
-            // site 0's left neighbour (site L - 1) is not yet visited: no flip
-            const int32_t n1 = x == 0u ? n0 : (int32_t)(4u * (cnt + (ml ^ 1u)));
-            desc[4 * m + k] = ilp_cand<MODEL>(n0, plus) | (ilp_cand<MODEL>(n1, plus) << 16);
-            if (m == (R::kCalls - 1) / LPC && k == 3) {
-                // the row's last site with site 0 flipped: its right neighbour toggles
-                const uint32_t cnt2 = ((pmr >> bit) & 1u) ? cnt - 1u : cnt + 1u;
-                dlast = ilp_cand<MODEL>((int32_t)(4u * (cnt2 + ml)), plus) |
-                        (ilp_cand<MODEL>((int32_t)(4u * (cnt2 + (ml ^ 1u))), plus) << 16);
-            }
+            // site 4 call + 3 of the last call is the row's last site: no next site
+            const uint32_t nextoff = (k == 3 && last) ? 0u : hoff[k + 1];
+            const uint32_t D = nextoff | (hds[k] << 16);
+            pk[4 * m + k] = (uint64_t)D | ((uint64_t)rng.w[4 * m + k] << 32);
+        }
+        if (m == (R::kCalls - 1) / LPC) {
+            dv2 = hoffv | (hds[2] << 16); // site L - 2: the last site's offsets
+            dv1 = hdsv << 16;             // site L - 1: its own bin steps
         }
     }
     uint32_t F[W];
 #pragma unroll
     for (int wi = 0; wi < W; ++wi)
         F[wi] = 0u;
-    ilp_sites<MODEL, L, LPC, TLDS>(desc, dlast, rng, rowb, F, T, std::make_integer_sequence<int, L>{});
+    ilp_sites<MODEL, L, LPC, TLDS>(pk, dv2, dv1, first, rowb, F, T, std::make_integer_sequence<int, L>{});
+    // the flips were shifted in from the low end, first site highest
 #pragma unroll
-    for (int wi = 0; wi < W; ++wi)
-        cur[wi] ^= F[wi];
+    for (int wi = 0; wi < W; ++wi) {
+        const int nb = (L - 32 * wi) < 32 ? (L - 32 * wi) : 32;
+        cur[wi] ^= __builtin_bitreverse32(F[wi]) >> (32 - nb);
+    }
 }
 
 // Storage <-> packed row.  BYTE storage holds int8 +1 (0x01) / -1 (0xFF),

@@ -115,6 +115,26 @@ def test_invariant_to_launch_shape_lanes_and_table_placement(model, layout, q):
                 assert np.array_equal(s, o.spins) and np.array_equal(b, o.bins()), (lpc, threads, tlds)
 
 
+@pytest.mark.parametrize("model,layout", [("ising", 1), ("ising", 2), ("muma", 1)])
+@pytest.mark.parametrize("L", [48, 64])
+def test_two_word_rows_lane_splits_and_table_placement(model, L, layout):
+    """Rows of two 32-site words, where a lane of 4 per chain owns several
+    Philox calls of a row: identical chains for 4 and 16 lanes per chain,
+    threshold table in LDS (where it fits) and in global memory."""
+    print(f"{model} L={L} layout={layout}", flush=True)
+    o, _ = pair(model, L, 96, seed=60 + L, layout=layout)
+    H = o.sweeps(4)
+    fits = not (model == "muma" and L == 64)
+    for lpc in (4, 16):
+        for tlds in ((0, 1) if fits else (0,)):
+            _, g = pair(model, L, 96, seed=60 + L, layout=layout, tlds=tlds, lpc=lpc)
+            g.run_iteration(4)
+            g.merge_update()
+            s, b, _ = g.chain_state()
+            assert np.array_equal(g.last_hist(), H), (lpc, tlds)
+            assert np.array_equal(s, o.spins) and np.array_equal(b, o.bins()), (lpc, tlds)
+
+
 def test_chunked_iteration_equals_one_piece():
     _, a = pair("ising", 16, 64, seed=8)
     _, b = pair("ising", 16, 64, seed=8)
