@@ -654,7 +654,9 @@ struct PottsLP {
     static constexpr bool ok = (LPC == 4 || LPC == 16) && L % LPC == 0;
     static constexpr int S = L / LPC;       // sites per lane
     static constexpr int SW = (S + 3) / 4;  // words of a lane's segment
-    static constexpr int NCALL = S / 2 + 1; // Philox calls that cover S sites from any first site
+    // Philox calls (two sites each) that cover the segment: S / 2 when S is
+    // even (segments start on even sites), else S / 2 + 1 (either parity)
+    static constexpr int NCALL = S % 2 == 0 ? S / 2 : S / 2 + 1;
 };
 
 // Segment of row y owned by lane j: sites [S j, S j + S) in bytes 0..S-1.
@@ -701,16 +703,26 @@ __device__ __forceinline__ void lp_store(uint32_t *base, size_t stride, int y, u
     }
 }
 
-// Threshold-row offset and column code of a site with c = dE + 4:
-// low 8 bits the byte offset of the column in the bin's row (8 staged
-// columns in LDS, c = 8 in column 4; 9 columns in global memory), bits 8..15
-// the code c.
+// Column offset (bytes) of the code c = dE + 4 in a bin's threshold row: 8
+// staged columns in LDS (c = 8 in column 4; c = 4 is never read), 9 columns
+// in global memory.
 template <bool TLDS>
-__device__ __forceinline__ uint32_t lp_cand(uint32_t c)
+__device__ __forceinline__ uint32_t lp_off(uint32_t c)
 {
-    const uint32_t col = TLDS ? ((c ^ ((c >> 1) & 4u)) & 7u) : c;
-    return (col << 2) | (c << 8);
+    return TLDS ? ((c ^ ((c >> 1) & 4u)) & 7u) << 2 : c << 2;
 }
+
+// Shift (bytes) of the bin row origin when a move with code c is accepted.
+template <bool TLDS>
+__device__ __forceinline__ int32_t lp_ds(uint32_t c)
+{
+    return ((int32_t)c - 4) * (TLDS ? 32 : 36);
+}
+
+// Acceptance word of a candidate, accept iff word <= T: r + 1 (r clamped to
+// 2^32 - 2, so r + 1 <= T iff r < T) when the move changes the energy, 0 for
+// dE = 0, which is accepted whatever threshold is read for it.
+__device__ __forceinline__ uint32_t lp_word(uint32_t c, uint32_t r) { return c == 4u ? 0u : r + 1u; }
 
 // c = dE + 4 for the colours of a site: old, proposal nw, the fixed
 // neighbours (down, up, right or filler) packed with a 0xFF filler byte in
@@ -727,74 +739,91 @@ __device__ __forceinline__ uint32_t lp_code(uint32_t nb, uint32_t old, uint32_t 
            (lft == nw ? 1u : 0u);
 }
 
-// Descriptor pair of site X (rejected / accepted left neighbour), from the
-// owning lane; the row's last site uses the variant for site 0's outcome.
+// Descriptors of site X from its owning lane, two 64-bit broadcasts:
+//   geo: bytes 0, 1 = the next site's column offsets (this site rejected /
+//        accepted); high dword = this site's bin shifts as two int16 (left
+//        neighbour rejected / accepted);
+//   acw: the site's acceptance words (left neighbour rejected / accepted).
+// Sites L - 2 and L - 1 switch to their variants when site 0 was accepted
+// (it is the right neighbour of site L - 1).
 template <int L, int LPC, int X>
-__device__ __forceinline__ uint32_t lp_pair(const uint32_t (&pr)[PottsLP<L, LPC>::S], uint32_t pl2, uint32_t F0)
+__device__ __forceinline__ void lp_get(const uint64_t (&geo)[PottsLP<L, LPC>::S],
+                                       const uint64_t (&acw)[PottsLP<L, LPC>::S], uint64_t gv2, uint64_t gv1,
+                                       uint64_t av1, bool f0, uint64_t &g, uint64_t &w)
 {
-    constexpr int S = PottsLP<L, LPC>::S;
-    uint32_t pair = group_bcast<LPC, X / S>(pr[X % S]);
-    if constexpr (X == L - 1 && L > 1) {
-        const uint32_t p2 = group_bcast<LPC, X / S>(pl2);
-        pair = (F0 & 1u) ? p2 : pair;
+    constexpr int S = PottsLP<L, LPC>::S, O = X / S, R = X % S;
+    g = group_bcast64<LPC, O>(geo[R]);
+    w = group_bcast64<LPC, O>(acw[R]);
+    if constexpr (X == L - 2) {
+        const uint64_t v = group_bcast64<LPC, O>(gv2);
+        g = f0 ? v : g;
     }
-    return pair;
+    if constexpr (X == L - 1) {
+        const uint64_t v = group_bcast64<LPC, O>(gv1), u = group_bcast64<LPC, O>(av1);
+        g = f0 ? v : g;
+        w = f0 ? u : w;
+    }
 }
 
-// Site X.  Its two candidate thresholds (t0: previous site rejected, t1:
-// accepted) and codes were read during the previous site; `rowb` and `dstep`
-// are those of the previous site's attempt.  Before this site's compare, the
-// next site's two candidate thresholds are read, so each LDS read has a whole
-// site to complete and the loop-carried chain is select -> compare.
+// Site X.  On entry: B / Bf = the bin row origin before this site's attempt
+// if the previous site was rejected / accepted, prev = that outcome, (t0, t1)
+// = this site's threshold in either case (read one site earlier), (g, w) =
+// its descriptors.  The next site's two candidate thresholds are read before
+// this site's compare, so each read has a whole site to complete and the
+// loop-carried chain is select -> compare.
 template <int L, int LPC, bool TLDS, int X>
-__device__ __forceinline__ void lp_site(const uint32_t (&pr)[PottsLP<L, LPC>::S], uint32_t pl2,
-                                        const uint32_t (&ra)[PottsLP<L, LPC>::S], int32_t &rowb, int32_t &dstep,
-                                        bool &prev, uint32_t &t0, uint32_t &t1, uint32_t &c0, uint32_t &c1,
-                                        uint32_t &F0, uint32_t &F1, const uint32_t *__restrict__ T)
+__device__ __forceinline__ void lp_site(const uint64_t (&geo)[PottsLP<L, LPC>::S],
+                                        const uint64_t (&acw)[PottsLP<L, LPC>::S], uint64_t gv2, uint64_t gv1,
+                                        uint64_t av1, int32_t &B, int32_t &Bf, uint64_t &g, uint64_t &w, bool &prev,
+                                        bool &f0, uint64_t &pm, uint32_t &t0, uint32_t &t1, uint32_t (&F)[2],
+                                        const uint32_t *__restrict__ T)
 {
-    constexpr int S = PottsLP<L, LPC>::S;
-    rowb += prev ? dstep : 0; // the row of this site's attempt
-    const uint32_t c = prev ? c1 : c0;
-    dstep = TLDS ? (int32_t)(c << 5) - 128 : (int32_t)c * 36 - 144;
-    const uint32_t r = group_bcast<LPC, X / S>(ra[X % S]);
-    uint32_t n_t0 = 0u, n_t1 = 0u, n_c0 = 0u, n_c1 = 0u;
+    const uint32_t glo = (uint32_t)g, ghi = (uint32_t)(g >> 32);
+    const int32_t x0 = B + (int32_t)(int16_t)(ghi & 0xFFFFu), x1 = Bf + ((int32_t)ghi >> 16);
+    B = prev ? Bf : B;   // this site's bin row
+    Bf = prev ? x1 : x0; // the next site's, if this one is accepted
+    const uint32_t word = prev ? (uint32_t)(w >> 32) : (uint32_t)w;
+    uint32_t n_t0 = 0u, n_t1 = 0u;
+    uint64_t ng = 0u, nw = 0u;
     if constexpr (X + 1 < L) {
-        const uint32_t pair = lp_pair<L, LPC, X + 1>(pr, pl2, F0);
-        n_t0 = load_t<TLDS>(T, rowb + (int32_t)(pair & 0xFFu));
-        n_t1 = load_t<TLDS>(T, rowb + dstep + (int32_t)((pair >> 16) & 0xFFu));
-        n_c0 = (pair >> 8) & 0xFFu;
-        n_c1 = pair >> 24;
+        n_t0 = load_t<TLDS>(T, B + sbyte(glo));
+        n_t1 = load_t<TLDS>(T, Bf + sbyte(glo >> 8));
+        lp_get<L, LPC, X + 1>(geo, acw, gv2, gv1, av1, f0, ng, nw);
     }
-    // selected only now, after the next reads were issued; the scheduling
-    // barrier keeps the compiler from pulling this select (and its wait for
-    // the reads) up against the reads just issued
+    // selected only now, after the next reads were issued (the barrier keeps
+    // the wait for this site's reads one site behind them)
     __builtin_amdgcn_sched_barrier(0);
     const uint32_t t = prev ? t1 : t0;
     t0 = n_t0;
     t1 = n_t1;
-    c0 = n_c0;
-    c1 = n_c1;
-    const bool acc = (r < t) | (c == 4u);
-    if constexpr (X < 32)
-        F0 |= (acc ? 1u : 0u) << X;
-    else
-        F1 |= (acc ? 1u : 0u) << (X - 32);
+    g = ng;
+    w = nw;
+    if constexpr (X > 0)
+        F[(X - 1) / 32] = shift_in<false>(F[(X - 1) / 32], pm);
+    const bool acc = word <= t;
+    if constexpr (X == 0)
+        f0 = acc;
+    pm = __builtin_amdgcn_ballot_w64(acc);
     prev = acc;
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 template <int L, int LPC, bool TLDS, int... X>
-__device__ __forceinline__ void lp_row(const uint32_t (&pr)[PottsLP<L, LPC>::S], uint32_t pl2,
-                                       const uint32_t (&ra)[PottsLP<L, LPC>::S], int32_t &rowb, uint32_t &F0,
-                                       uint32_t &F1, const uint32_t *__restrict__ T, std::integer_sequence<int, X...>)
+__device__ __forceinline__ void lp_row(const uint64_t (&geo)[PottsLP<L, LPC>::S],
+                                       const uint64_t (&acw)[PottsLP<L, LPC>::S], uint64_t gv2, uint64_t gv1,
+                                       uint64_t av1, uint32_t first, int32_t &rowb, uint32_t (&F)[2],
+                                       const uint32_t *__restrict__ T, std::integer_sequence<int, X...>)
 {
-    // site 0: the left neighbour (site L - 1) is not yet visited, one candidate
-    const uint32_t p0 = lp_pair<L, LPC, 0>(pr, pl2, 0u);
-    uint32_t t0 = load_t<TLDS>(T, rowb + (int32_t)(p0 & 0xFFu)), t1 = t0;
-    uint32_t c0 = (p0 >> 8) & 0xFFu, c1 = c0;
-    int32_t dstep = 0;
-    bool prev = false;
-    (lp_site<L, LPC, TLDS, X>(pr, pl2, ra, rowb, dstep, prev, t0, t1, c0, c1, F0, F1, T), ...);
-    rowb += prev ? dstep : 0;
+    uint64_t g, w;
+    lp_get<L, LPC, 0>(geo, acw, gv2, gv1, av1, false, g, w);
+    // site 0: its left neighbour (site L - 1) is not yet visited, one candidate
+    uint32_t t0 = load_t<TLDS>(T, rowb + sbyte(group_bcast<LPC, 0>(first))), t1 = t0;
+    int32_t B = rowb, Bf = rowb;
+    bool prev = false, f0 = false;
+    uint64_t pm = 0u;
+    (lp_site<L, LPC, TLDS, X>(geo, acw, gv2, gv1, av1, B, Bf, g, w, prev, f0, pm, t0, t1, F, T), ...);
+    F[(L - 1) / 32] = shift_in<true>(F[(L - 1) / 32], pm);
+    rowb = prev ? Bf : B;
 }
 
 // The sweeps of one chain (per lane: its segment), with the histogram
@@ -815,7 +844,7 @@ __device__ __forceinline__ int32_t potts_lp_sweeps(const LatticeArgs &a, uint32_
     lp_load<L, LPC>(base, stride, 2 % L, j, nx);
     int32_t rowb = TLDS ? tbase + 32 * b : 36 * b;
     auto bin_of = [&](int32_t rb) { return TLDS ? (rb - tbase) >> 5 : rb / 36; };
-    const uint32_t first = ((uint32_t)S * j) >> 1, par = ((uint32_t)S * j) & 1u;
+    const uint32_t first_call = ((uint32_t)S * j) >> 1, par = ((uint32_t)S * j) & 1u;
     const bool lane0 = j == 0u, lanel = j == (uint32_t)(LPC - 1);
     int until_flush = flush_every;
     for (int s = 0; s < a.n_sweeps; ++s) {
@@ -826,7 +855,8 @@ __device__ __forceinline__ int32_t potts_lp_sweeps(const LatticeArgs &a, uint32_
             uint32_t w[NCALL][4];
 #pragma unroll
             for (int k = 0; k < NCALL; ++k) {
-                const uint32_t call = first + (uint32_t)k < (uint32_t)KC ? first + (uint32_t)k : (uint32_t)KC - 1u;
+                const uint32_t call =
+                    first_call + (uint32_t)k < (uint32_t)KC ? first_call + (uint32_t)k : (uint32_t)KC - 1u;
                 const Words4 r = philox4x32_10(chain, g, (uint32_t)(y * KC) + call, kTagSweep, a.k0, a.k1);
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
@@ -846,7 +876,7 @@ __device__ __forceinline__ int32_t potts_lp_sweeps(const LatticeArgs &a, uint32_
                     wp = (w[(m + 1) / 2][2 * ((m + 1) & 1)] & mk) | (w[m / 2][2 * (m & 1)] & ~mk);
                     wa = (w[(m + 1) / 2][2 * ((m + 1) & 1) + 1] & mk) | (w[m / 2][2 * (m & 1) + 1] & ~mk);
                 }
-                ra[m] = min(wa, 0xFFFFFFFEu); // accept iff ra < T
+                ra[m] = min(wa, 0xFFFFFFFEu);
                 old[m] = (cur[m / 4] >> (8 * (m % 4))) & 0xFFu;
                 const uint32_t n = old[m] + 1u + __umulhi(wp, q - 1u);
                 nw[m] = min(n, n - q); // n - q wraps above n when n < q
@@ -858,7 +888,11 @@ __device__ __forceinline__ int32_t potts_lp_sweeps(const LatticeArgs &a, uint32_
             const uint32_t l0_acc = lane0 ? lh_old : lh_nw;
             // the right neighbour of the row's last site is site 0, visited first
             const uint32_t rr_acc = lanel ? rh_nw : rh_old;
-            uint32_t pr[S], pl2 = 0u;
+            // per site: both candidates' offsets, bin shifts and acceptance words
+            uint32_t offp[S], dsp[S];
+            uint64_t acw[S];
+            uint32_t offv = 0u, dsv = 0u;
+            uint64_t av1 = 0u;
 #pragma unroll
             for (int m = 0; m < S; ++m) {
                 // bytes: down, up (same column), right, filler
@@ -874,16 +908,37 @@ __device__ __forceinline__ int32_t potts_lp_sweeps(const LatticeArgs &a, uint32_
                     nb = __builtin_amdgcn_perm(vert, rh_old, 4u | (5u << 8) | (0u << 16) | (0x0Du << 24));
                 const uint32_t l_rej = m > 0 ? old[m > 0 ? m - 1 : 0] : lh_old;
                 const uint32_t l_acc = m > 0 ? nw[m > 0 ? m - 1 : 0] : l0_acc;
-                pr[m] = lp_cand<TLDS>(lp_code(nb, old[m], nw[m], l_rej)) |
-                        (lp_cand<TLDS>(lp_code(nb, old[m], nw[m], l_acc)) << 16);
+                const uint32_t c0 = lp_code(nb, old[m], nw[m], l_rej), c1 = lp_code(nb, old[m], nw[m], l_acc);
+                offp[m] = lp_off<TLDS>(c0) | (lp_off<TLDS>(c1) << 8);
+                dsp[m] = ((uint32_t)lp_ds<TLDS>(c0) & 0xFFFFu) | ((uint32_t)lp_ds<TLDS>(c1) << 16);
+                acw[m] = (uint64_t)lp_word(c0, ra[m]) | ((uint64_t)lp_word(c1, ra[m]) << 32);
                 if (m + 1 == S) {
+                    // the row's last site (lane LPC - 1) with site 0 accepted
                     const uint32_t nb2 = __builtin_amdgcn_perm(vert, rr_acc, 4u | (5u << 8) | (0x0Du << 24));
-                    pl2 = lp_cand<TLDS>(lp_code(nb2, old[m], nw[m], l_rej)) |
-                          (lp_cand<TLDS>(lp_code(nb2, old[m], nw[m], l_acc)) << 16);
+                    const uint32_t v0 = lp_code(nb2, old[m], nw[m], l_rej), v1 = lp_code(nb2, old[m], nw[m], l_acc);
+                    offv = lp_off<TLDS>(v0) | (lp_off<TLDS>(v1) << 8);
+                    dsv = ((uint32_t)lp_ds<TLDS>(v0) & 0xFFFFu) | ((uint32_t)lp_ds<TLDS>(v1) << 16);
+                    av1 = (uint64_t)lp_word(v0, ra[m]) | ((uint64_t)lp_word(v1, ra[m]) << 32);
                 }
             }
-            uint32_t F0 = 0u, F1 = 0u;
-            lp_row<L, LPC, TLDS>(pr, pl2, ra, rowb, F0, F1, T, std::make_integer_sequence<int, L>{});
+            // the next site's offsets: the lane's own, or site 0 of the next
+            // lane's segment for its last site (none after the row's last site)
+            const uint32_t next0 = group_next<LPC>(offp[0]), nextv = group_next<LPC>(offv);
+            uint64_t geo[S];
+#pragma unroll
+            for (int m = 0; m < S; ++m) {
+                const uint32_t nxo = m + 1 < S ? offp[m + 1 < S ? m + 1 : 0] : (lanel ? 0u : next0);
+                geo[m] = (uint64_t)nxo | ((uint64_t)dsp[m] << 32);
+            }
+            // site L - 2 with site 0 accepted: the last site's offsets change
+            const uint64_t gv2 =
+                (uint64_t)(S >= 2 ? offv : nextv) | ((uint64_t)dsp[S >= 2 ? S - 2 : 0] << 32);
+            const uint64_t gv1 = (uint64_t)dsv << 32;
+            uint32_t F[2] = {0u, 0u};
+            lp_row<L, LPC, TLDS>(geo, acw, gv2, gv1, av1, offp[0], rowb, F, T, std::make_integer_sequence<int, L>{});
+            // flips were shifted in from the low end, first site highest
+            const uint32_t F0 = __builtin_bitreverse32(F[0]) >> (32 - (L < 32 ? L : 32));
+            const uint32_t F1 = L > 32 ? __builtin_bitreverse32(F[1]) >> (32 - (L > 32 ? L - 32 : 32)) : 0u;
             // this lane's accepted proposals: bits S j .. S j + S - 1 of F
             const uint32_t fj = (uint32_t)((((uint64_t)F1 << 32) | F0) >> (S * j));
 #pragma unroll
