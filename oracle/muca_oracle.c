@@ -28,6 +28,10 @@
  *   orc_flatness      "flat energy distribution" stopping rule (paper,
  *                     parallel-scheme paragraph).
  *   orc_reweight      reweighting to canonical expectation values (Eq. 2).
+ *   orc_sweeps_em,    multimagnetic runs (Eq. 3) with the joint histogram of
+ *   orc_reweight_em   E and the flattened M, reweighted to the canonical
+ *                     ensemble at another inverse temperature (Eq. 2 with the
+ *                     MUMA weight in place of W(E)).
  *   orc_polymer_*     bead-spring homopolymer with LJ + FENE (Eq. 7) and
  *                     single-monomer shift moves.
  */
@@ -274,9 +278,9 @@ static int accept(uint32_t T, uint32_t r)
 /* Run n_sweeps sweeps (global sweep ids g0, g0+1, ...) of chains
  * [ch_lo, ch_hi).  A sweep visits sites 0..N-1 in row-major order; after each
  * sweep the chain's bin is added to H if record != 0.  E and M are carried. */
-int orc_sweeps(const orc_lattice *c, int8_t *spins, int32_t *E, int32_t *M,
-               const uint32_t *T, uint32_t g0, int64_t n_sweeps, int record,
-               uint64_t *H, int32_t ch_lo, int32_t ch_hi)
+static int sweeps_impl(const orc_lattice *c, int8_t *spins, int32_t *E, int32_t *M,
+                       const uint32_t *T, uint32_t g0, int64_t n_sweeps, int record,
+                       uint64_t *H, uint64_t *HEM, int32_t ch_lo, int32_t ch_hi)
 {
     int32_t L = c->L, N = L * L, nc = orc_ncols(c->model), B = orc_nbins(c);
     int32_t step = bin_step(c->model), ch;
@@ -347,10 +351,34 @@ int orc_sweeps(const orc_lattice *c, int8_t *spins, int32_t *E, int32_t *M,
                 if (b < 0 || b >= B)
                     return -1;
                 H[b] += 1u;
+                if (HEM) {
+                    /* E = -2N + 4e, e = 0..N: the row of the joint histogram */
+                    int32_t e = (E[ch] + 2 * N) / 4;
+                    HEM[(int64_t)e * B + b] += 1u;
+                }
             }
         }
     }
     return 0;
+}
+
+int orc_sweeps(const orc_lattice *c, int8_t *spins, int32_t *E, int32_t *M,
+               const uint32_t *T, uint32_t g0, int64_t n_sweeps, int record,
+               uint64_t *H, int32_t ch_lo, int32_t ch_hi)
+{
+    return sweeps_impl(c, spins, E, M, T, g0, n_sweeps, record, H, NULL, ch_lo, ch_hi);
+}
+
+/* orc_sweeps of a MUMA run that also counts every recorded sweep in
+ * HEM[e * B + b] (e = (E + 2N) / 4, b = the magnetisation bin), the state
+ * after the sweep.  -2 if the run is not multimagnetic. */
+int orc_sweeps_em(const orc_lattice *c, int8_t *spins, int32_t *E, int32_t *M,
+                  const uint32_t *T, uint32_t g0, int64_t n_sweeps, int record,
+                  uint64_t *H, uint64_t *HEM, int32_t ch_lo, int32_t ch_hi)
+{
+    if (c->model != ORC_MUMA)
+        return -2;
+    return sweeps_impl(c, spins, E, M, T, g0, n_sweeps, record, H, HEM, ch_lo, ch_hi);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -492,6 +520,69 @@ void orc_reweight(int32_t B, const uint64_t *H, const double *lnW, const double 
         out[2] = mean;
         out[3] = amax + log(Z);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reweighting of a multimagnetic run to the canonical ensemble at beta2.    */
+/* The run samples states with weight exp(-beta E) W(M) (Eq. 3); the         */
+/* canonical weight at beta2 relative to that is exp(-(beta2 - beta) E)/W(M),*/
+/* so over the joint histogram HEM[e][b] (E_e = Ev[e], M_b = Mv[b]):         */
+/*   a = ln HEM[e][b] - lnW[b] - (beta2 - beta) E_e,  w = exp(a - max a),    */
+/*   out = { <E>/N, beta2^2 Var(E)/N, <|M|>/N, <M^2>/N^2,                   */
+/*           beta2 (<M^2> - <|M|>^2)/N, max a + ln sum w }.                  */
+/* Sums run over e, then b, ascending; the variance of E is a second pass    */
+/* around the mean.                                                          */
+/* ------------------------------------------------------------------------ */
+void orc_reweight_em(int32_t NE, int32_t B, const uint64_t *HEM, const double *lnW, const double *Ev,
+                     const double *Mv, int32_t nsite, double beta, double beta2, double *out)
+{
+    int32_t e, b, any = 0;
+    double amax = 0.0, Z = 0.0, s_e = 0.0, s_am = 0.0, s_m2 = 0.0, mean, var = 0.0, n = (double)nsite;
+    for (e = 0; e < NE; ++e)
+        for (b = 0; b < B; ++b) {
+            double a;
+            if (HEM[(int64_t)e * B + b] == 0)
+                continue;
+            a = log((double)HEM[(int64_t)e * B + b]) - lnW[b] - (beta2 - beta) * Ev[e];
+            if (!any || a > amax)
+                amax = a;
+            any = 1;
+        }
+    if (!any) {
+        for (e = 0; e < 6; ++e)
+            out[e] = 0.0;
+        return;
+    }
+    for (e = 0; e < NE; ++e)
+        for (b = 0; b < B; ++b) {
+            double a, w;
+            if (HEM[(int64_t)e * B + b] == 0)
+                continue;
+            a = log((double)HEM[(int64_t)e * B + b]) - lnW[b] - (beta2 - beta) * Ev[e];
+            w = exp(a - amax);
+            Z += w;
+            s_e += w * Ev[e];
+            s_am += w * fabs(Mv[b]);
+            s_m2 += w * (Mv[b] * Mv[b]);
+        }
+    mean = s_e / Z;
+    for (e = 0; e < NE; ++e)
+        for (b = 0; b < B; ++b) {
+            double a, w, d;
+            if (HEM[(int64_t)e * B + b] == 0)
+                continue;
+            a = log((double)HEM[(int64_t)e * B + b]) - lnW[b] - (beta2 - beta) * Ev[e];
+            w = exp(a - amax);
+            d = Ev[e] - mean;
+            var += w * (d * d);
+        }
+    var = var / Z;
+    out[0] = mean / n;
+    out[1] = beta2 * beta2 * var / n;
+    out[2] = (s_am / Z) / n;
+    out[3] = (s_m2 / Z) / (n * n);
+    out[4] = beta2 * ((s_m2 / Z) - (s_am / Z) * (s_am / Z)) / n;
+    out[5] = amax + log(Z);
 }
 
 /* ------------------------------------------------------------------------ */

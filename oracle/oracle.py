@@ -85,6 +85,12 @@ def lib():
         L.orc_sweeps.argtypes = [P(_Lattice), i8p, i32p, i32p, u32p, ctypes.c_uint32,
                                  ctypes.c_int64, ctypes.c_int, u64p, ctypes.c_int32, ctypes.c_int32]
         L.orc_sweeps.restype = ctypes.c_int
+        L.orc_sweeps_em.argtypes = [P(_Lattice), i8p, i32p, i32p, u32p, ctypes.c_uint32,
+                                    ctypes.c_int64, ctypes.c_int, u64p, u64p, ctypes.c_int32, ctypes.c_int32]
+        L.orc_sweeps_em.restype = ctypes.c_int
+        L.orc_reweight_em.argtypes = [ctypes.c_int32, ctypes.c_int32, u64p, f64p, f64p, f64p, ctypes.c_int32,
+                                      ctypes.c_double, ctypes.c_double, f64p]
+        L.orc_reweight_em.restype = None
         L.orc_recursion.argtypes = [ctypes.c_int32, u8p, u64p, f64p, f64p, f64p]
         L.orc_flatness.argtypes = [ctypes.c_int32, u8p, u64p]
         L.orc_flatness.restype = ctypes.c_double
@@ -230,6 +236,36 @@ class LatticeRun:
     def advance(self, n: int):
         self.sweep += n
 
+    @property
+    def em_shape(self) -> tuple[int, int]:
+        """Joint (E, M) histogram of a multimagnetic run: rows e = 0..N for
+        E = -2N + 4e, columns the magnetisation bins."""
+        return self.L * self.L + 1, self.n_bins
+
+    def sweeps_em(self, n: int, HEM: np.ndarray, T: np.ndarray | None = None,
+                  H: np.ndarray | None = None) -> np.ndarray:
+        """sweeps() of a MUMA run that also adds each sweep's (E, M bin) to HEM."""
+        if T is None:
+            T = self.thresholds()
+        T = np.ascontiguousarray(T, np.uint32)
+        if H is None:
+            H = np.zeros(self.n_bins, np.uint64)
+        assert HEM.dtype == np.uint64 and HEM.shape == self.em_shape and HEM.flags.c_contiguous
+        rc = lib().orc_sweeps_em(ctypes.byref(self._c), _ptr(self.spins, ctypes.c_int8),
+                                 _ptr(self.E, ctypes.c_int32), _ptr(self.M, ctypes.c_int32),
+                                 _ptr(T, ctypes.c_uint32), ctypes.c_uint32(self.sweep & 0xffffffff),
+                                 ctypes.c_int64(n), 1, _ptr(H, ctypes.c_uint64), _ptr(HEM, ctypes.c_uint64),
+                                 0, self.n_chains)
+        if rc != 0:
+            raise RuntimeError("not a multimagnetic run" if rc == -2 else "oracle chain left the binned range")
+        return H
+
+    def reweight_em(self, HEM, lnW, betas) -> np.ndarray:
+        """Canonical averages at each beta' from the joint histogram of
+        sweeps run with weights lnW: rows of { <E>/N, beta'^2 Var(E)/N,
+        <|M|>/N, <M^2>/N^2, beta' (<M^2> - <|M|>^2)/N, ln Z }."""
+        return reweight_em(HEM, lnW, self.L, self.lo, self.beta, betas)
+
     def merge_update(self, H: np.ndarray) -> float:
         """Accumulated-statistics recursion on the merged histogram; returns flatness."""
         H = np.ascontiguousarray(H, np.uint64)
@@ -292,6 +328,25 @@ def reweight(H, lnW, values, nsite, beta, muma=False):
                        _ptr(v, ctypes.c_double), nsite, int(muma), ctypes.c_double(beta),
                        _ptr(o, ctypes.c_double))
     return o
+
+
+def reweight_em(HEM, lnW, L, lo, beta, betas) -> np.ndarray:
+    """orc_reweight_em over the rows E = -2N + 4e and the columns
+    M = lo + 2b of a multimagnetic run at inverse temperature beta."""
+    N = L * L
+    HEM = np.ascontiguousarray(HEM, np.uint64)
+    lnW = np.ascontiguousarray(lnW, np.float64)
+    NE, B = HEM.shape
+    Ev = -2.0 * N + 4.0 * np.arange(NE, dtype=np.float64)
+    Mv = lo + 2.0 * np.arange(B, dtype=np.float64)
+    out = np.zeros((len(betas), 6), np.float64)
+    for k, b2 in enumerate(betas):
+        o = np.zeros(6, np.float64)
+        lib().orc_reweight_em(NE, B, _ptr(HEM, ctypes.c_uint64), _ptr(lnW, ctypes.c_double),
+                              _ptr(Ev, ctypes.c_double), _ptr(Mv, ctypes.c_double), N,
+                              ctypes.c_double(beta), ctypes.c_double(b2), _ptr(o, ctypes.c_double))
+        out[k] = o
+    return out
 
 
 # --------------------------------------------------------------------------
