@@ -172,3 +172,17 @@ def paper_systems() -> list[tuple[System, list[int], int]]:
         (System("potts", 16, q=8, potts_law=True), pw[4:12], 8),
         (System("muma", 16, beta=1.5 * BETA_C), pw[:11], 16),
     ]
+
+
+def q_scan_systems(L: int = 16, qs=range(2, 11), ps=None, replicas: int = 8) -> list[tuple[System, list[int], int]]:
+    """The q-state Potts crossover scan of the paper's q figure (second-order
+    transition for q <= 4, weakly first order at q = 5, first order above):
+    S*_p for every q at one lattice size.  The paper extrapolates M_opt per q
+    without printing the values; here q = 2 takes the Ising law of Eq. 4 and
+    q >= 3 the 8-state Potts law (the per-unit energy bins of q >= 3 need the
+    statistics of the latter).  The paper's lattice is 64 x 64, whose
+    smallest-p iterations do not fit one GPU's time budget; the default is
+    16 x 16 with p = 16 .. 2048."""
+    ps = list(ps) if ps is not None else [2 ** k for k in range(4, 12)]
+    return [(System("potts", L, q=q, potts_law=q >= 3), ps, replicas) for q in qs]
+

@@ -27,7 +27,8 @@ def oracle_trace(system, p, seed, sweeps, max_iters):
 
 
 @pytest.mark.parametrize("spec", [("ising", 8, 2, 0.0, False), ("potts", 8, 3, 0.0, True),
-                                  ("muma", 8, 2, 0.661, False)])
+                                  ("muma", 8, 2, 0.661, False), ("potts", 8, 2, 0.0, False),
+                                  ("potts", 8, 10, 0.0, True)])
 def test_iterations_to_flat_equal_the_oracle(spec):
     from paper_1312_2213_amd import speedup as su
     model, L, q, beta, law = spec

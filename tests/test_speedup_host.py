@@ -57,3 +57,16 @@ def test_seeds_distinct():
 def test_muma_at_two_thirds_tc():
     (sysm,) = [s for s, _, _ in su.paper_systems() if s.model == "muma"]
     assert sysm.beta == pytest.approx(1.5 * 0.5 * math.log(1 + math.sqrt(2)))
+
+
+def test_q_scan_laws_and_grid():
+    """q = 2 is the Ising model (Ising law), q >= 3 the per-unit Potts
+    energies (8-state Potts law); every q on the same p grid."""
+    sc = su.q_scan_systems(16)
+    assert [s.q for s, _, _ in sc] == list(range(2, 11))
+    assert all(s.model == "potts" and s.L == 16 for s, _, _ in sc)
+    assert [s.potts_law for s, _, _ in sc] == [False] + [True] * 8
+    assert all(ps == [16, 32, 64, 128, 256, 512, 1024, 2048] and r == 8 for _, ps, r in sc)
+    assert sc[0][0].sweeps(16) == math.ceil(5.7 * 16 ** 2.51 / 16)
+    assert sc[6][0].sweeps(16) == math.ceil(24 * 16 ** 2.67 / 16)
+
