@@ -18,8 +18,11 @@ region.  The line also carries:
 Other modes (--workload): "batched" (time to flat, batched vs plain),
 "serving" (200 Poisson requests, p50/p99 time to flat), "polymer" (N = 40,
 4096 chains), "polymer_paper" (the paper's homopolymer, N = 40 and 80),
-"speedup" (statistical speedup S*_p over chains per run, Eq. 6),
-"copy" (device copy of known size, for counter calibration).
+"speedup" (statistical speedup S*_p over chains per run, Eq. 6; with
+--speedup-set qscan the q-state Potts crossover scan), "muma_em"
+(multimagnetic run at T = 2/3 T_c with the joint (E, M) histogram reweighted
+in beta, and the cost of recording it), "copy" (device copy of known size,
+for counter calibration).
 """
 from __future__ import annotations
 
@@ -49,7 +52,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ising64",
-                    choices=["ising64", "batched", "serving", "polymer", "polymer_paper", "speedup", "copy"])
+                    choices=["ising64", "batched", "serving", "polymer", "polymer_paper", "speedup", "muma_em",
+                             "copy"])
     ap.add_argument("--sweeps", type=int, default=10000, help="sweeps per iteration (workload: 10^4)")
     ap.add_argument("--lanes-per-chain", type=int, default=0)
     ap.add_argument("--batch-lanes-per-chain", type=int, default=0, help="batched runs: 4, 16 or 0 (per run)")
@@ -314,6 +318,65 @@ def bench_polymer_paper(args):
     return None
 
 
+def bench_muma_em(args):
+    """Multimagnetic Ising at the paper's T = 2/3 T_c (beta = 1.5 beta_c):
+    weights iterated until the M histogram is flat, then a production run
+    that records the joint (E, M) histogram, reweighted to temperatures
+    around the run's; and the cost of that recording on the sweep kernel
+    (4096 chains, L = 32, 1000 sweeps, with and without)."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1312_2213_amd import muca
+    from synth.workloads import sweeps_per_iteration
+    beta_c = 0.5 * math.log(1.0 + math.sqrt(2.0))
+    beta = 1.5 * beta_c
+    L, C = 16, 1024
+    stream = torch.cuda.current_stream()
+    run = muca.Run(muca.muca_config_default("muma", L, 2, C, 9, beta=beta, layout=muca.MUCA_LAYOUT_BIT),
+                   stream=stream)
+    S = sweeps_per_iteration(L, C, False)
+    t0 = time.perf_counter()
+    n_it, flat = 0, False
+    while n_it < args.max_iters and not flat:
+        run.run_iteration(S)
+        flat = run.merge_update()["flat"]
+        n_it += 1
+    t_conv = time.perf_counter() - t0
+    ne, nm = run.em_shape()
+    em = torch.zeros(ne * nm, dtype=torch.int64, device="cuda")
+    P = 200
+    run.run_iteration_em(P, em)
+    run.merge_update()
+    h = em.cpu().numpy().view(np.uint64).reshape(ne, nm)
+    betas = [beta * f for f in (0.9, 0.95, 1.0, 1.05, 1.1)]
+    rw = run.reweight_em(h, betas)
+    # recording cost: same run shape with and without the joint histogram
+    big = muca.Run(muca.muca_config_default("muma", 32, 2, 4096, 3, beta=beta, layout=muca.MUCA_LAYOUT_BIT),
+                   stream=stream)
+    ne2, nm2 = big.em_shape()
+    em2 = torch.zeros(ne2 * nm2, dtype=torch.int64, device="cuda")
+    ms = {}
+    for mode in ("plain", "em", "plain", "em"):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if mode == "em":
+            big.run_iteration_em(1000, em2)
+        else:
+            big.run_iteration(1000)
+        e1.record(stream)
+        big.merge_update()
+        ms[mode] = e0.elapsed_time(e1)
+    return {"metric": "multimagnetic run with joint (E, M) histogram, reweighted in beta (1 GPU)",
+            "config": {"workload": f"MUMA Ising L={L}, beta = 1.5 beta_c = {beta:.6f}, {C} chains, seed 9, "
+                                   f"{S} sweeps per iteration until flat, then {P} production sweeps"},
+            "iterations_to_flat": n_it, "flat": bool(flat), "seconds_to_flat": t_conv,
+            "reweighted": [{"beta": b, "e": r[0], "c": r[1], "abs_m": r[2], "m2": r[3], "chi": r[4]}
+                           for b, r in zip(betas, rw.tolist())],
+            "em_cost": {"workload": "MUMA L=32, 4096 chains, 1000 sweeps", "plain_ms": ms["plain"],
+                        "em_ms": ms["em"], "overhead": ms["em"] / ms["plain"] - 1.0}}
+
+
 def bench_polymer(args, N=40, params=None, walk=None):
     import numpy as np
     import torch
@@ -387,7 +450,7 @@ def main():
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
         sys.exit(2)
     if args.max_iters is None:
-        args.max_iters = {"serving": 3000, "speedup": 1000}.get(args.workload, 40)
+        args.max_iters = {"serving": 3000, "speedup": 1000, "muma_em": 1000}.get(args.workload, 40)
     if args.workload == "ising64":
         out = bench_ising64(args)
     elif args.workload == "batched":
@@ -400,6 +463,8 @@ def main():
         out = bench_polymer_paper(args)
     elif args.workload == "speedup":
         out = bench_speedup(args)
+    elif args.workload == "muma_em":
+        out = bench_muma_em(args)
     else:
         out = bench_copy()
     if out is not None:

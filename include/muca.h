@@ -165,6 +165,31 @@ int muca_merge_update_hist(muca_run *run, const uint64_t *h, int64_t n, muca_ite
  * Potts energies are E_unsat - 2N; polymer bins use their centres. */
 int muca_reweight(const muca_run *run, const double *betas, int32_t n, double *out);
 
+/* Joint (E, M) histogram of a multimagnetic run, for reweighting in the
+ * temperature (multimagnetic paragraph: the run flattens M at a fixed beta;
+ * with E recorded beside M, Eq. 2 with the weight exp(-beta E) W(M) of Eq. 3
+ * in place of W(E) gives canonical averages at any beta' near beta).
+ *   muca_em_shape: n_e = N + 1 energy rows (row e holds E = -2N + 4e), n_m =
+ *     the number of magnetisation bins.  MUCA_E_ARG if the run is not MUMA.
+ *   muca_run_iteration_em: muca_run_iteration that also adds, for every
+ *     chain and sweep, one count to d_em[e * n_m + b], e and b those of the
+ *     configuration the sweep left.  d_em: device memory of n_e * n_m
+ *     uint64, owned by the caller, accumulated into and never cleared.  The
+ *     chains, the histogram H and the sweep counter are those of
+ *     muca_run_iteration.  MUCA_E_ARG for a run that is not MUMA, a null
+ *     d_em or sweeps < 1.
+ *   muca_reweight_em: for each betas[k], out[6k..6k+5] = { <E>/N,
+ *     beta'^2 Var(E)/N, <|M|>/N, <M^2>/N^2, beta' (<M^2> - <|M|>^2)/N,
+ *     ln sum_{e,b} h W_b^-1 e^(-(beta' - beta) E_e) } over the host copy
+ *     h_em (n_em = n_e * n_m entries) of a joint histogram recorded with the
+ *     weights of the last merged iteration (the lnW^(n) of muca_reweight).
+ *     MUCA_E_STATE before the first merge, MUCA_E_ARG for a size mismatch,
+ *     null pointers or n < 1. */
+int muca_em_shape(const muca_run *run, int32_t *n_e, int32_t *n_m);
+int muca_run_iteration_em(muca_run *run, int64_t sweeps, uint64_t *d_em, void *stream);
+int muca_reweight_em(const muca_run *run, const uint64_t *h_em, int64_t n_em, const double *betas, int32_t n,
+                     double *out);
+
 /* Batched iterations (one persistent launch for several lattice runs of
  * mixed model, L, q, ensemble and layout).  The runs' chains are cut into
  * work items of 256 / lanes_per_chain chains that a grid sized to the chip

@@ -507,6 +507,32 @@ __device__ __forceinline__ void ising_lp_row(const uint32_t (&up)[Row1<L>::W], u
     }
 }
 
+// Unsatisfied bonds of bit-packed rows: horizontal bonds of one row
+// (periodic), vertical bonds between two rows.
+template <int L>
+__device__ __forceinline__ uint32_t row_mis(const uint32_t (&R)[Row1<L>::W])
+{
+    constexpr int W = Row1<L>::W;
+    uint32_t n = 0u;
+#pragma unroll
+    for (int wi = 0; wi < W; ++wi) {
+        const int nb = (L - 32 * wi) < 32 ? (L - 32 * wi) : 32;
+        const uint32_t nextbit = (wi + 1 < W) ? (R[wi + 1 < W ? wi + 1 : 0] & 1u) : (R[0] & 1u);
+        n += (uint32_t)__builtin_popcount(R[wi] ^ ((R[wi] >> 1) | (nextbit << (nb - 1))));
+    }
+    return n;
+}
+
+template <int L>
+__device__ __forceinline__ uint32_t pair_mis(const uint32_t (&A)[Row1<L>::W], const uint32_t (&B)[Row1<L>::W])
+{
+    uint32_t n = 0u;
+#pragma unroll
+    for (int wi = 0; wi < Row1<L>::W; ++wi)
+        n += (uint32_t)__builtin_popcount(A[wi] ^ B[wi]);
+    return n;
+}
+
 // Storage <-> packed row.  BYTE storage holds int8 +1 (0x01) / -1 (0xFF),
 // four sites per word; bit 1 of a byte is set exactly for -1.
 template <int L, int LAYOUT>
@@ -1079,6 +1105,11 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
         if constexpr (TLDS)
             tbase = (int32_t)(uint32_t)(uintptr_t)(lds_u32 *)smem;
         int32_t rowb = tbase + 4 * (b * NC + row_origin<MODEL>());
+        // MUMA with the joint (E, M) histogram: unsatisfied bonds of the
+        // sweep's final configuration, counted row by row once a row and the
+        // one above it are final (the bond between rows L - 1 and 0 last)
+        const bool em = MODEL == kMuma && a.em != nullptr;
+        uint32_t nmis = 0u;
         for (int s = 0; s < a.n_sweeps; ++s) {
             const uint32_t g = a.g0 + (uint32_t)s;
             for (int y = 0; y < L; ++y) {
@@ -1087,6 +1118,13 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
                 else
                     ising_row<MODEL, L, LPC, TLDS>(up, cur, dn, rowb, T, chain, g, y, j, a.k0, a.k1,
                                                    std::make_integer_sequence<int, W>{});
+                if constexpr (MODEL == kMuma) {
+                    if (em) {
+                        nmis += row_mis<L>(cur) + (y > 0 ? pair_mis<L>(up, cur) : 0u);
+                        if (y == L - 1)
+                            nmis += pair_mis<L>(cur, dn); // dn: row 0 as this sweep left it
+                    }
+                }
                 if (leader)
                     store_row<L, LAYOUT>(base, stride, y, cur);
 #pragma unroll
@@ -1100,7 +1138,15 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
             if (counts) {
                 const int32_t bb = (((rowb - tbase) >> 2) - row_origin<MODEL>()) / NC;
                 atomicAdd(&lhist[bb >> 1], 1u << ((bb & 1) << 4));
+                if constexpr (MODEL == kMuma) {
+                    if (em) { // E = -2N + 2 nmis = -2N + 4 e, e <= N
+                        const uint32_t e = min(nmis >> 1, (uint32_t)(L * L));
+                        atomicAdd(&a.em[(size_t)e * (size_t)a.n_bins + (size_t)bb], 1ull);
+                    }
+                }
             }
+            if constexpr (MODEL == kMuma)
+                nmis = 0u;
             if (--until_flush == 0 && s + 1 < a.n_sweeps) {
                 until_flush = flush_every;
                 __syncthreads();

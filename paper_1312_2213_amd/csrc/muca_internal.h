@@ -27,6 +27,9 @@ struct LatticeArgs {
     int32_t record;             // histogram the sweeps
     int32_t table_in_lds;
     int32_t chain0;             // global index of the first chain handled
+    // MUMA only, or null: joint histogram [(N + 1) * n_bins] of the energy
+    // row e = (E + 2N) / 4 and the magnetisation bin after each recorded sweep
+    unsigned long long *em;
 };
 
 struct LatticeInitArgs {

@@ -524,7 +524,7 @@ extern "C" int muca_init(const muca_config *c, void *d_ws, uint64_t ws_bytes, co
     return MUCA_OK;
 }
 
-int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s)
+int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s, unsigned long long *em)
 {
     if (r->g.model == kPolymer)
         return muca_polymer_enqueue(r, sweeps, record, s);
@@ -551,6 +551,7 @@ int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s)
         a.record = record ? 1 : 0;
         a.table_in_lds = g.table_in_lds ? 1 : 0;
         a.chain0 = r->cfg.chain0;
+        a.em = em;
         HIP_OR_POISON(r, launch_lattice_sweeps(g.model, g.L, g.layout, g.lpc, g.cpb, a, s));
         r->sweep += (uint32_t)n;
         done += n;
@@ -567,6 +568,39 @@ extern "C" int muca_run_iteration(muca_run *r, int64_t sweeps, void *stream)
         return muca_fail(MUCA_E_ARG, "sweeps must be >= 1");
     r->stream = (hipStream_t)stream;
     rc = muca_enqueue_sweeps(r, sweeps, true, r->stream);
+    if (rc)
+        return rc;
+    r->pending += sweeps;
+    return MUCA_OK;
+}
+
+extern "C" int muca_em_shape(const muca_run *r, int32_t *n_e, int32_t *n_m)
+{
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (r->g.model != kMuma)
+        return muca_fail(MUCA_E_ARG, "joint (E, M) histogram: multimagnetic runs only");
+    if (n_e)
+        *n_e = r->g.n_sites + 1;
+    if (n_m)
+        *n_m = r->g.n_bins;
+    return MUCA_OK;
+}
+
+extern "C" int muca_run_iteration_em(muca_run *r, int64_t sweeps, uint64_t *d_em, void *stream)
+{
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (r->g.model != kMuma)
+        return muca_fail(MUCA_E_ARG, "joint (E, M) histogram: multimagnetic runs only");
+    if (!d_em)
+        return muca_fail(MUCA_E_ARG, "null joint histogram");
+    if (sweeps < 1)
+        return muca_fail(MUCA_E_ARG, "sweeps must be >= 1");
+    r->stream = (hipStream_t)stream;
+    rc = muca_enqueue_sweeps(r, sweeps, true, r->stream, (unsigned long long *)d_em);
     if (rc)
         return rc;
     r->pending += sweeps;
@@ -694,6 +728,82 @@ extern "C" int muca_reweight(const muca_run *r, const double *betas, int32_t n, 
         muca_reweight_bins(g.n_bins, r->H_last.data(), r->lnW_last.data(), val.data(), g.n_sites, muma,
                            beta, out + 4 * k);
     }
+    return MUCA_OK;
+}
+
+// Canonical averages at beta2 from the joint histogram of a multimagnetic run
+// at beta with log weights lnW: each state's canonical weight relative to its
+// sampling weight exp(-beta E) W(M) is exp(-(beta2 - beta) E) / W(M).
+static void reweight_joint(int NE, int B, const uint64_t *h, const double *lnW, int32_t lo, int32_t mstep,
+                           int nsite, double beta, double beta2, double *out)
+{
+    auto energy = [&](int e) { return -2.0 * nsite + 4.0 * e; };
+    auto magnet = [&](int b) { return (double)lo + (double)mstep * b; };
+    auto log_w = [&](int e, int b) {
+        return std::log((double)h[(size_t)e * B + b]) - lnW[b] - (beta2 - beta) * energy(e);
+    };
+    double amax = 0.0;
+    bool any = false;
+    for (int e = 0; e < NE; ++e)
+        for (int b = 0; b < B; ++b)
+            if (h[(size_t)e * B + b]) {
+                const double a = log_w(e, b);
+                if (!any || a > amax)
+                    amax = a;
+                any = true;
+            }
+    if (!any) {
+        for (int k = 0; k < 6; ++k)
+            out[k] = 0.0;
+        return;
+    }
+    double Z = 0.0, sE = 0.0, sA = 0.0, s2 = 0.0;
+    for (int e = 0; e < NE; ++e)
+        for (int b = 0; b < B; ++b)
+            if (h[(size_t)e * B + b]) {
+                const double w = std::exp(log_w(e, b) - amax), m = magnet(b);
+                Z += w;
+                sE += w * energy(e);
+                sA += w * std::fabs(m);
+                s2 += w * (m * m);
+            }
+    const double mean = sE / Z;
+    double var = 0.0;
+    for (int e = 0; e < NE; ++e)
+        for (int b = 0; b < B; ++b)
+            if (h[(size_t)e * B + b]) {
+                const double w = std::exp(log_w(e, b) - amax), d = energy(e) - mean;
+                var += w * (d * d);
+            }
+    var /= Z;
+    const double n = (double)nsite, mA = sA / Z, m2 = s2 / Z;
+    out[0] = mean / n;
+    out[1] = beta2 * beta2 * var / n;
+    out[2] = mA / n;
+    out[3] = m2 / (n * n);
+    out[4] = beta2 * (m2 - mA * mA) / n;
+    out[5] = amax + std::log(Z);
+}
+
+extern "C" int muca_reweight_em(const muca_run *r, const uint64_t *h_em, int64_t n_em, const double *betas,
+                                int32_t n, double *out)
+{
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    const Geometry &g = r->g;
+    if (g.model != kMuma)
+        return muca_fail(MUCA_E_ARG, "joint (E, M) histogram: multimagnetic runs only");
+    if (!r->have_last)
+        return muca_fail(MUCA_E_STATE, "no merged histogram yet");
+    const int NE = g.n_sites + 1, B = g.n_bins;
+    if (!h_em || n_em != (int64_t)NE * B)
+        return muca_fail(MUCA_E_ARG, "joint histogram of %lld entries, expected %d x %d", (long long)n_em, NE, B);
+    if (n < 1 || !betas || !out)
+        return muca_fail(MUCA_E_ARG, "need n >= 1, betas and an output array");
+    for (int k = 0; k < n; ++k)
+        reweight_joint(NE, B, h_em, r->lnW_last.data(), r->cfg.lo, g.step, g.n_sites, r->cfg.beta, betas[k],
+                       out + 6 * k);
     return MUCA_OK;
 }
 

@@ -69,6 +69,9 @@ def _load():
         "muca_get_pending_hist": (ctypes.c_int, [vp, vp, i64]),
         "muca_merge_update_hist": (ctypes.c_int, [vp, vp, i64, P(muca_iter_stats)]),
         "muca_reweight": (ctypes.c_int, [vp, vp, i32, vp]),
+        "muca_em_shape": (ctypes.c_int, [vp, P(i32), P(i32)]),
+        "muca_run_iteration_em": (ctypes.c_int, [vp, i64, vp, vp]),
+        "muca_reweight_em": (ctypes.c_int, [vp, vp, i64, vp, i32, vp]),
         "muca_batch_workspace_bytes": (ctypes.c_int, [i32, i32, P(ctypes.c_uint64)]),
         "muca_batch_create": (ctypes.c_int, [i32, i32, i32, i32, vp, u64, P(vp)]),
         "muca_batch_run_iteration": (ctypes.c_int, [vp, P(vp), i32, P(ctypes.c_int64), vp]),
@@ -96,7 +99,8 @@ def _load():
 LIB = _load()
 EXPORTED = ("muca_config_default", "muca_workspace_bytes", "muca_init", "muca_run_iteration",
             "muca_thermalize", "muca_merge_update", "muca_get_pending_hist", "muca_merge_update_hist",
-            "muca_reweight", "muca_batch_workspace_bytes",
+            "muca_reweight", "muca_em_shape", "muca_run_iteration_em", "muca_reweight_em",
+            "muca_batch_workspace_bytes",
             "muca_batch_create", "muca_batch_run_iteration", "muca_batch_free", "muca_autotune", "muca_sizes", "muca_get_lnw", "muca_get_last_hist",
             "muca_get_thresholds", "muca_get_chain_state", "muca_set_lnw", "muca_set_thresholds",
             "muca_checkpoint", "muca_restore", "muca_free", "muca_last_error")
@@ -161,6 +165,34 @@ class Run:
     # -- the hot path ------------------------------------------------------
     def run_iteration(self, sweeps: int, stream=None):
         _check(LIB.muca_run_iteration(self.handle, int(sweeps), _stream_handle(stream or self.stream)))
+
+    def em_shape(self) -> tuple[int, int]:
+        """(n_e, n_m) of the joint (E, M) histogram of a multimagnetic run."""
+        ne, nm = ctypes.c_int32(), ctypes.c_int32()
+        _check(LIB.muca_em_shape(self.handle, ctypes.byref(ne), ctypes.byref(nm)))
+        return ne.value, nm.value
+
+    def run_iteration_em(self, sweeps: int, em, stream=None):
+        """run_iteration that also counts each sweep in `em`, a contiguous
+        64-bit integer device tensor of em_shape() entries (accumulated into,
+        never cleared; counts are read as uint64)."""
+        import torch
+        ne, nm = self.em_shape()
+        if not (isinstance(em, torch.Tensor) and em.is_cuda and em.dtype in (torch.uint64, torch.int64)
+                and em.is_contiguous() and em.numel() == ne * nm):
+            raise ValueError(f"em must be a contiguous 64-bit integer CUDA tensor of {ne} x {nm}")
+        _check(LIB.muca_run_iteration_em(self.handle, int(sweeps), ctypes.c_void_p(em.data_ptr()),
+                                         _stream_handle(stream or self.stream)))
+
+    def reweight_em(self, h_em, betas) -> np.ndarray:
+        """Canonical averages at each beta' from a host joint histogram
+        recorded with the last merged iteration's weights: rows of
+        { <E>/N, beta'^2 Var(E)/N, <|M|>/N, <M^2>/N^2, beta' (<M^2> - <|M|>^2)/N, ln Z }."""
+        h = np.ascontiguousarray(h_em, np.uint64)
+        b = np.ascontiguousarray(np.atleast_1d(betas), np.float64)
+        out = np.zeros((len(b), 6), np.float64)
+        _check(LIB.muca_reweight_em(self.handle, _ptr(h), h.size, _ptr(b), len(b), _ptr(out)))
+        return out
 
     def thermalize(self, sweeps: int, stream=None):
         _check(LIB.muca_thermalize(self.handle, int(sweeps), _stream_handle(stream or self.stream)))
