@@ -33,7 +33,9 @@
  *                     ensemble at another inverse temperature (Eq. 2 with the
  *                     MUMA weight in place of W(E)).
  *   orc_polymer_*     bead-spring homopolymer with LJ + FENE (Eq. 7) and
- *                     single-monomer shift moves.
+ *                     single-monomer shift moves; optionally the paper's full
+ *                     move set (shift, spherical rotation, double bridging,
+ *                     polymer paragraph), in the forms stated at the moves.
  */
 #include <math.h>
 #include <stdint.h>
@@ -78,6 +80,8 @@ void orc_philox(const uint32_t ctr[4], uint64_t seed, uint32_t out[4])
 /* Stream layout: counter = (chain, sweep, block, tag), key = seed. */
 #define ORC_TAG_SWEEP 0u
 #define ORC_TAG_INIT 1u
+#define ORC_TAG_ROT 2u    /* polymer spherical rotations */
+#define ORC_TAG_BRIDGE 3u /* polymer double bridging */
 
 static void draw(uint64_t seed, uint32_t chain, uint32_t sweep, uint32_t block,
                  uint32_t tag, uint32_t out[4])
@@ -605,6 +609,8 @@ typedef struct {
     double lj_eps, lj_sigma, lj_rcut;
     double fene_k, fene_r0, fene_R;
     float step;        /* side of the displacement cube                  */
+    int32_t moves;     /* 0: shifts; 1: shifts, spherical rotations and   */
+                       /* double bridging (the paper's move set)          */
 } orc_polymer;
 
 static double lj_shift(const orc_polymer *p)
@@ -614,27 +620,39 @@ static double lj_shift(const orc_polymer *p)
     return 4.0 * p->lj_eps * (sr6 * sr6 - sr6);
 }
 
-/* energy of one pair at squared distance r2; returns 0 if a bond is broken
- * (and sets *broken) */
-static double pair_energy(const orc_polymer *p, int32_t i, int32_t j, double r2, int *broken)
+/* FENE bond energy at squared length r2; 0 and *broken = 1 outside the
+ * bond's domain */
+static double fene(const orc_polymer *p, double r2, int *broken)
 {
-    int32_t sep = i > j ? i - j : j - i;
-    if (sep == 1) {
-        double r = sqrt(r2);
-        double t = (r - p->fene_r0) / p->fene_R;
-        double arg = 1.0 - t * t;
-        if (!(arg > 0.0)) {
-            *broken = 1;
-            return 0.0;
-        }
-        return -(0.5 * p->fene_k * p->fene_R * p->fene_R) * log(arg);
+    double r = sqrt(r2);
+    double t = (r - p->fene_r0) / p->fene_R;
+    double arg = 1.0 - t * t;
+    if (!(arg > 0.0)) {
+        *broken = 1;
+        return 0.0;
     }
+    return -(0.5 * p->fene_k * p->fene_R * p->fene_R) * log(arg);
+}
+
+/* cut and shifted Lennard-Jones energy at squared distance r2 */
+static double lj(const orc_polymer *p, double r2)
+{
     if (r2 < p->lj_rcut * p->lj_rcut) {
         double sr2 = (p->lj_sigma * p->lj_sigma) / r2;
         double sr6 = sr2 * sr2 * sr2;
         return 4.0 * p->lj_eps * (sr6 * sr6 - sr6) - lj_shift(p);
     }
     return 0.0;
+}
+
+/* energy of one pair at squared distance r2; returns 0 if a bond is broken
+ * (and sets *broken) */
+static double pair_energy(const orc_polymer *p, int32_t i, int32_t j, double r2, int *broken)
+{
+    int32_t sep = i > j ? i - j : j - i;
+    if (sep == 1)
+        return fene(p, r2, broken);
+    return lj(p, r2);
 }
 
 static double dist2(const float *a, const float *b)
@@ -718,6 +736,133 @@ static double polymer_delta(const orc_polymer *p, const float *pos, int32_t i,
     return t[0];
 }
 
+/* Spherical rotation of bead i (the paper names the move; its form here):
+ * an inner bead turns about the line through its two neighbours, an end
+ * bead about a coordinate axis (chosen by word 1) through its neighbour, so
+ * every bond length is kept.  The rotation is that of the quaternion
+ * (tau, a), a the axis direction, not normalised: angle 2 atan2(|a|, tau).
+ * tau comes from word 0: u = (k - (2^23 - 1/2)) / 2^23 in (-1, 1) for
+ * k = w >> 8, tau = u / (1 - |u|), so tau and -tau (the inverse rotation)
+ * are equally likely and the proposal is symmetric.  Only +, -, *, / in
+ * double, in the order written, then one rounding to float per axis. */
+static double rot_tau(uint32_t w)
+{
+    double u = ((double)(w >> 8) - 8388607.5) / 8388608.0;
+    return u / (1.0 - fabs(u));
+}
+
+static void quat_rotate(double w, const double a[3], const double v[3], double out[3])
+{
+    double x = a[0], y = a[1], z = a[2];
+    double ww = w * w, xx = x * x, yy = y * y, zz = z * z;
+    double n2 = ((ww + xx) + yy) + zz;
+    double m00 = ((ww + xx) - yy) - zz, m11 = ((ww - xx) + yy) - zz, m22 = ((ww - xx) - yy) + zz;
+    double m01 = 2.0 * (x * y - w * z), m02 = 2.0 * (x * z + w * y);
+    double m10 = 2.0 * (x * y + w * z), m12 = 2.0 * (y * z - w * x);
+    double m20 = 2.0 * (x * z - w * y), m21 = 2.0 * (y * z + w * x);
+    out[0] = ((m00 * v[0] + m01 * v[1]) + m02 * v[2]) / n2;
+    out[1] = ((m10 * v[0] + m11 * v[1]) + m12 * v[2]) / n2;
+    out[2] = ((m20 * v[0] + m21 * v[1]) + m22 * v[2]) / n2;
+}
+
+static void rotation_proposal(const orc_polymer *p, const float *x, int32_t i, const uint32_t w[4],
+                              float xn[3])
+{
+    int32_t nb = p->n_beads, k, ctr;
+    double a[3], v[3], r[3], c[3];
+    if (i > 0 && i < nb - 1) {
+        ctr = i - 1;
+        for (k = 0; k < 3; ++k)
+            a[k] = (double)x[3 * (i + 1) + k] - (double)x[3 * (i - 1) + k];
+    } else {
+        uint32_t ax = (uint32_t)(((uint64_t)w[1] * 3u) >> 32);
+        ctr = i == 0 ? 1 : nb - 2;
+        for (k = 0; k < 3; ++k)
+            a[k] = (uint32_t)k == ax ? 1.0 : 0.0;
+    }
+    for (k = 0; k < 3; ++k) {
+        c[k] = (double)x[3 * ctr + k];
+        v[k] = (double)x[3 * i + k] - c[k];
+    }
+    quat_rotate(rot_tau(w[0]), a, v, r);
+    for (k = 0; k < 3; ++k)
+        xn[k] = (float)(c[k] + r[k]);
+}
+
+/* Double bridging (the paper names the move; its form here): bonds (i, i+1)
+ * and (j, j+1), i + 2 <= j, are replaced by (i, j) and (i+1, j+1) and the
+ * beads i+1 .. j are renumbered in reverse, so the chain stays linear and
+ * no bead moves.  i and j come from words 0 and 1 (uniform in 0 .. N-2,
+ * ordered; pairs closer than 2 do nothing); the move is its own inverse.
+ * Energy change: the four bonds swap between FENE and LJ:
+ *   dE = ((F(ij) + F(i+1,j+1)) - F(i,i+1)) - F(j,j+1)
+ *      + ((L(i,i+1) + L(j,j+1)) - L(ij)) - L(i+1,j+1).
+ * Returns 1 and sets *dE, *pi, *pj for a proposal, 0 for none or a new bond
+ * outside the FENE domain. */
+static int bridging_proposal(const orc_polymer *p, const float *x, const uint32_t w[4], double *dE,
+                             int32_t *pi, int32_t *pj)
+{
+    int32_t nb = p->n_beads, i, j, t;
+    int broken = 0;
+    double fij, fkl, fik, fjl, lij, lkl, lik, ljl, dF, dL;
+    if (nb < 4)
+        return 0;
+    i = (int32_t)(((uint64_t)w[0] * (uint64_t)(nb - 1)) >> 32);
+    j = (int32_t)(((uint64_t)w[1] * (uint64_t)(nb - 1)) >> 32);
+    if (i > j) {
+        t = i;
+        i = j;
+        j = t;
+    }
+    if (j - i < 2)
+        return 0;
+    /* new bonds (i, j), (i+1, j+1); old bonds (i, i+1), (j, j+1) */
+    fij = fene(p, dist2(x + 3 * i, x + 3 * j), &broken);
+    fkl = fene(p, dist2(x + 3 * (i + 1), x + 3 * (j + 1)), &broken);
+    if (broken)
+        return 0;
+    fik = fene(p, dist2(x + 3 * i, x + 3 * (i + 1)), &broken);
+    fjl = fene(p, dist2(x + 3 * j, x + 3 * (j + 1)), &broken);
+    lij = lj(p, dist2(x + 3 * i, x + 3 * j));
+    lkl = lj(p, dist2(x + 3 * (i + 1), x + 3 * (j + 1)));
+    lik = lj(p, dist2(x + 3 * i, x + 3 * (i + 1)));
+    ljl = lj(p, dist2(x + 3 * j, x + 3 * (j + 1)));
+    dF = ((fij + fkl) - fik) - fjl;
+    dL = ((lik + ljl) - lij) - lkl;
+    *dE = dF + dL;
+    *pi = i;
+    *pj = j;
+    return 1;
+}
+
+/* test hooks: the proposals of one chain (pos[bead][3]) */
+void orc_polymer_rotation(const orc_polymer *p, const float *pos, int32_t i, const uint32_t w[4], float xn[3])
+{
+    rotation_proposal(p, pos, i, w, xn);
+}
+
+int orc_polymer_bridging(const orc_polymer *p, const float *pos, const uint32_t w[4], double *dE, int32_t *i,
+                         int32_t *j)
+{
+    return bridging_proposal(p, pos, w, dE, i, j);
+}
+
+/* MUCA acceptance of a proposal with energy change dE for chain ch; on
+ * acceptance E and the bin advance */
+static int polymer_accept(const orc_polymer *p, const double *lnW, double *E, int32_t *bin, double dE,
+                          uint32_t word)
+{
+    double En = *E + dE;
+    int32_t bn = orc_polymer_bin(p, En);
+    if (bn < 0)
+        return 0;
+    if (!accept(threshold(lnW[bn] - lnW[*bin]), word))
+        return 0;
+    *E = En;
+    *bin = bn;
+    return 1;
+}
+
 /* T2 is the B x B threshold matrix T2[b*B + b'] of lnW(b') - lnW(b); pass
  * NULL to evaluate the rule from lnW directly (same values). */
 int orc_polymer_sweeps(const orc_polymer *p, float *pos, double *E, int32_t *bin,
@@ -756,6 +901,43 @@ int orc_polymer_sweeps(const orc_polymer *p, float *pos, double *E, int32_t *bin
                     x[3 * i + 2] = xn[2];
                     E[ch] = En;
                     bin[ch] = bn;
+                }
+            }
+            if (p->moves) {
+                int32_t bi, bj, k;
+                double dEb;
+                /* a spherical rotation of every bead, in order */
+                for (i = 0; i < nb; ++i) {
+                    uint32_t w[4];
+                    float xn[3];
+                    int broken = 0;
+                    double dE;
+                    draw(p->seed, (uint32_t)ch, g, (uint32_t)i, ORC_TAG_ROT, w);
+                    rotation_proposal(p, x, i, w, xn);
+                    dE = polymer_delta(p, x, i, xn, &broken);
+                    if (broken)
+                        continue;
+                    if (polymer_accept(p, lnW, &E[ch], &bin[ch], dE, w[3])) {
+                        x[3 * i + 0] = xn[0];
+                        x[3 * i + 1] = xn[1];
+                        x[3 * i + 2] = xn[2];
+                    }
+                }
+                /* one double-bridging attempt */
+                {
+                    uint32_t w[4];
+                    draw(p->seed, (uint32_t)ch, g, 0u, ORC_TAG_BRIDGE, w);
+                    if (bridging_proposal(p, x, w, &dEb, &bi, &bj) &&
+                        polymer_accept(p, lnW, &E[ch], &bin[ch], dEb, w[3])) {
+                        for (i = bi + 1, k = bj; i < k; ++i, --k) {
+                            int32_t d;
+                            for (d = 0; d < 3; ++d) {
+                                float tmp = x[3 * i + d];
+                                x[3 * i + d] = x[3 * k + d];
+                                x[3 * k + d] = tmp;
+                            }
+                        }
+                    }
                 }
             }
             if (record)

@@ -56,7 +56,7 @@ class _Polymer(ctypes.Structure):
                 ("n_bins", ctypes.c_int32), ("lj_eps", ctypes.c_double),
                 ("lj_sigma", ctypes.c_double), ("lj_rcut", ctypes.c_double),
                 ("fene_k", ctypes.c_double), ("fene_r0", ctypes.c_double),
-                ("fene_R", ctypes.c_double), ("step", ctypes.c_float)]
+                ("fene_R", ctypes.c_double), ("step", ctypes.c_float), ("moves", ctypes.c_int32)]
 
 
 _lib = None
@@ -102,6 +102,11 @@ def lib():
         L.orc_polymer_bin.restype = ctypes.c_int32
         L.orc_polymer_init.argtypes = [P(_Polymer), f32p, f64p, i32p]
         L.orc_polymer_init.restype = ctypes.c_int
+        L.orc_polymer_rotation.argtypes = [P(_Polymer), f32p, ctypes.c_int32, u32p, f32p]
+        L.orc_polymer_rotation.restype = None
+        L.orc_polymer_bridging.argtypes = [P(_Polymer), f32p, u32p, P(ctypes.c_double), P(ctypes.c_int32),
+                                           P(ctypes.c_int32)]
+        L.orc_polymer_bridging.restype = ctypes.c_int
         L.orc_polymer_sweeps.argtypes = [P(_Polymer), f32p, f64p, i32p, f64p, ctypes.c_uint32,
                                          ctypes.c_int64, ctypes.c_int, u64p, ctypes.c_int32,
                                          ctypes.c_int32]
@@ -368,13 +373,14 @@ class PolymerRun:
     fene_r0: float = 1.0
     fene_R: float = 0.5
     step: float = 0.3
+    moves: int = 0                      # 1: shift + spherical rotation + double bridging
     sweep: int = 0
     iteration: int = 0
 
     def __post_init__(self):
         self._c = _Polymer(self.n_beads, self.n_chains, self.seed, self.x_lo, self.x_hi,
                            self.n_bins, self.lj_eps, self.lj_sigma, self.lj_rcut, self.fene_k,
-                           self.fene_r0, self.fene_R, self.step)
+                           self.fene_r0, self.fene_R, self.step, self.moves)
         self.pos = np.ascontiguousarray(self.pos, np.float32).reshape(
             self.n_chains, self.n_beads, 3).copy()
         self.E = np.zeros(self.n_chains, np.float64)
@@ -399,6 +405,24 @@ class PolymerRun:
 
     def bin_of(self, E: float) -> int:
         return int(lib().orc_polymer_bin(ctypes.byref(self._c), ctypes.c_double(E)))
+
+    def rotation(self, pos_one, i: int, words) -> np.ndarray:
+        """The spherical-rotation proposal of bead i of one conformation."""
+        p = np.ascontiguousarray(pos_one, np.float32)
+        w = np.ascontiguousarray(words, np.uint32)
+        out = np.zeros(3, np.float32)
+        lib().orc_polymer_rotation(ctypes.byref(self._c), _ptr(p, ctypes.c_float), i, _ptr(w, ctypes.c_uint32),
+                                   _ptr(out, ctypes.c_float))
+        return out
+
+    def bridging(self, pos_one, words):
+        """The double-bridging proposal of one conformation: (dE, i, j) or None."""
+        p = np.ascontiguousarray(pos_one, np.float32)
+        w = np.ascontiguousarray(words, np.uint32)
+        dE, i, j = ctypes.c_double(), ctypes.c_int32(), ctypes.c_int32()
+        ok = lib().orc_polymer_bridging(ctypes.byref(self._c), _ptr(p, ctypes.c_float), _ptr(w, ctypes.c_uint32),
+                                        ctypes.byref(dE), ctypes.byref(i), ctypes.byref(j))
+        return (dE.value, i.value, j.value) if ok else None
 
     def sweeps(self, n: int, record: bool = True, chains=None, H=None):
         c0, c1 = (0, self.n_chains) if chains is None else chains
