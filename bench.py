@@ -307,14 +307,20 @@ def bench_polymer_paper(args):
     N = 40 and 80, 4096 chains: one JSON line each."""
     from synth import PAPER_POLYMER
     pp = dict(PAPER_POLYMER)
-    for N in (40, 80):
-        out = bench_polymer(args, N=N, params=dict(pp, x_lo=-400.0, x_hi=100.0, n_bins=1000),
-                            walk=dict(bond=pp["fene_r0"], min_dist=pp["lj_sigma"]))
-        out["metric"] = "polymer displacement attempts/s, the paper's homopolymer (1 GPU)"
-        out["config"] = {"workload": f"bead-spring homopolymer with the paper's parameters (K=40, r0=0.7, "
-                                     f"r_max=1, sigma=2^(-1/6) r0, LJ uncut), N={N}, 4096 chains, seed 5, "
-                                     "1000 sweeps per iteration, 1000 bins on [-400, 100)"}
-        print(json.dumps(out), flush=True)
+    for moves in (0, 1):
+        for N in (40, 80):
+            out = bench_polymer(args, N=N, params=dict(pp, x_lo=-400.0, x_hi=100.0, n_bins=1000, moves=moves),
+                                walk=dict(bond=pp["fene_r0"], min_dist=pp["lj_sigma"]),
+                                per_sweep=N if moves == 0 else 2 * N + 1)
+            out["metric"] = ("polymer displacement attempts/s, the paper's homopolymer (1 GPU)" if moves == 0 else
+                             "polymer move attempts/s (shift, spherical rotation, double bridging), "
+                             "the paper's homopolymer (1 GPU)")
+            out["config"] = {"workload": f"bead-spring homopolymer with the paper's parameters (K=40, r0=0.7, "
+                                         f"r_max=1, sigma=2^(-1/6) r0, LJ uncut), N={N}, 4096 chains, seed 5, "
+                                         "1000 sweeps per iteration, 1000 bins on [-400, 100)"
+                                         + (", moves: N shifts + N rotations + 1 double bridging per sweep"
+                                            if moves else ", moves: N shifts per sweep")}
+            print(json.dumps(out), flush=True)
     return None
 
 
@@ -377,7 +383,7 @@ def bench_muma_em(args):
                         "em_ms": ms["em"], "overhead": ms["em"] / ms["plain"] - 1.0}}
 
 
-def bench_polymer(args, N=40, params=None, walk=None):
+def bench_polymer(args, N=40, params=None, walk=None, per_sweep=None):
     import numpy as np
     import torch
     from paper_1312_2213_amd import muca
@@ -401,7 +407,7 @@ def bench_polymer(args, N=40, params=None, walk=None):
         kern += e0.elapsed_time(e1)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    moves = C * N * S * args.steps
+    moves = C * (per_sweep or N) * S * args.steps
     return {"metric": "polymer displacement attempts/s (MUCA iteration, 1 GPU)", "value": moves / dt,
             "unit": "moves/s", "kernel_moves_per_s": moves / (kern * 1e-3), "ms_per_step": dt / args.steps * 1e3,
             "kernel_ms_per_step": kern / args.steps, "steps": args.steps,

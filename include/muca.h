@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MUCA_ABI_VERSION 2u
+#define MUCA_ABI_VERSION 3u
 
 typedef enum muca_status {
     MUCA_OK = 0,
@@ -75,7 +75,7 @@ typedef struct muca_config {
                                  must be 64, 128 or 256 threads              */
     int32_t table_in_lds;   /* -1 auto, 0 thresholds read from global memory, 1 staged in LDS */
     /* polymer */
-    int32_t n_beads;        /* 2..64                                           */
+    int32_t n_beads;        /* 2..128                                          */
     int32_t n_bins;         /* energy bins on [x_lo, x_hi)                     */
     double x_lo, x_hi;
     double lj_eps, lj_sigma, lj_rcut;
@@ -89,6 +89,14 @@ typedef struct muca_config {
                                be split into shards of consecutive chains (one
                                per device) that together give the unsplit run;
                                0 for a standalone run, >= 0                    */
+    int32_t moves;          /* polymer: 0 = single-bead shifts; 1 = the paper's
+                               move set (polymer paragraph): per sweep N shifts,
+                               N spherical rotations (bead i about the line
+                               through beads i-1 and i+1; an end bead about a
+                               coordinate axis through its neighbour) and one
+                               double bridging (bonds (i,i+1), (j,j+1) replaced
+                               by (i,j), (i+1,j+1), beads i+1..j renumbered in
+                               reverse).  0 for lattice runs.                 */
 } muca_config;
 
 typedef struct muca_iter_stats {

@@ -55,6 +55,7 @@ struct PolymerArgs {
     int32_t n_sweeps, n_chains, c_pad, n_bins, n_beads, record, chains_per_block;
     int32_t chain0;             // global index of chain 0 in the random-number counters
     float step;
+    int32_t moves;              // 1: spherical rotations and double bridging after the shifts
 };
 
 // Potential constants, each evaluated on the host once in a fixed order.

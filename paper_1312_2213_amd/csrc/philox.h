@@ -24,6 +24,8 @@ constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
 constexpr uint32_t kTagSweep = 0u;
 constexpr uint32_t kTagInit = 1u;
+constexpr uint32_t kTagRotate = 2u; // polymer spherical rotations
+constexpr uint32_t kTagBridge = 3u; // polymer double bridging
 
 struct Words4 {
     uint32_t w[4];

@@ -17,6 +17,15 @@
 // (lane k += lane k + s for s = 32, 16, ..., 1) built from lane permutes and
 // DPP moves, so the sum is the same number on every run.  The acceptance
 // threshold T[b][b'] of the bin change is one load from the B x B matrix.
+//
+// With the paper's move set (moves = 1) each sweep continues with a
+// spherical rotation of every bead (an inner bead about the line through its
+// neighbours, an end bead about a coordinate axis through its neighbour,
+// both by the quaternion (tau, axis) with tau symmetric about zero: only +,
+// -, *, / in FP64, so the proposal is bit-identical everywhere) and one
+// double bridging (two bonds swapped for two new ones, the beads between
+// renumbered in reverse by one lane permute); the energy change of a
+// rotation is the same lane-parallel tree sum as for a shift.
 #include <utility>
 
 #include "muca_internal.h"
@@ -128,6 +137,42 @@ __device__ __forceinline__ int32_t energy_bin(const PolyParams &p, double E, int
 __device__ __forceinline__ float from_lane(float v, int src)
 {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(v)));
+}
+
+__device__ __forceinline__ uint32_t from_lane_u32(uint32_t v, int src)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src * 4, (int)v);
+}
+
+__device__ __forceinline__ double from_lane_f64(double v, int src)
+{
+    const uint64_t u = __double_as_longlong(v);
+    const uint32_t lo = from_lane_u32((uint32_t)u, src), hi = from_lane_u32((uint32_t)(u >> 32), src);
+    return __longlong_as_double(((uint64_t)hi << 32) | lo);
+}
+
+// Rotation parameter of a 24-bit word: u = (k - (2^23 - 1/2)) / 2^23 in
+// (-1, 1), tau = u / (1 - |u|); the mirrored word gives -tau.
+__device__ __forceinline__ double rot_tau(uint32_t w)
+{
+    const double u = ((double)(w >> 8) - 8388607.5) / 8388608.0;
+    return u / (1.0 - __builtin_fabs(u));
+}
+
+// v' = R v for the quaternion (w, a) (not normalised): |q|^2 R applied to v,
+// divided by |q|^2; every product and sum in the order written.
+__device__ __forceinline__ void quat_rotate(double w, double x, double y, double z, double vx, double vy, double vz,
+                                            double &ox, double &oy, double &oz)
+{
+    const double ww = w * w, xx = x * x, yy = y * y, zz = z * z;
+    const double n2 = ((ww + xx) + yy) + zz;
+    const double m00 = ((ww + xx) - yy) - zz, m11 = ((ww - xx) + yy) - zz, m22 = ((ww - xx) - yy) + zz;
+    const double m01 = 2.0 * (x * y - w * z), m02 = 2.0 * (x * z + w * y);
+    const double m10 = 2.0 * (x * y + w * z), m12 = 2.0 * (y * z - w * x);
+    const double m20 = 2.0 * (x * z - w * y), m21 = 2.0 * (y * z + w * x);
+    ox = ((m00 * vx + m01 * vy) + m02 * vz) / n2;
+    oy = ((m10 * vx + m11 * vy) + m12 * vz) / n2;
+    oz = ((m20 * vx + m21 * vy) + m22 * vz) / n2;
 }
 
 // One chain per wavefront.  Lane j holds bead j and, with TWO (64 < N <= 128),
@@ -274,6 +319,151 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
                 b = bn;
             }
             prev_acc = acc;
+        }
+        if (a.moves) {
+            // position of bead k, the same in every lane
+            auto bead = [&](int k, float &px, float &py, float &pz) {
+                const int l = k & 63;
+                const bool h = TWO && k >= 64;
+                px = readlane_f32(h ? x[NS - 1].x : x[0].x, l);
+                py = readlane_f32(h ? x[NS - 1].y : x[0].y, l);
+                pz = readlane_f32(h ? x[NS - 1].z : x[0].z, l);
+            };
+            auto bond_of = [&](int k) { return readlane_f64((TWO && k >= 64) ? ub[NS - 1] : ub[0], k & 63); };
+            // spherical rotations, beads 0..N-1 in order
+            for (int i = 0; i < N; ++i) {
+                const Words4 w = philox4x32_10(chain, g, (uint32_t)i, kTagRotate, a.k0, a.k1);
+                float xi, yi, zi, lx = 0.f, ly = 0.f, lz = 0.f, rx = 0.f, ry = 0.f, rz = 0.f;
+                bead(i, xi, yi, zi);
+                if (i >= 1)
+                    bead(i - 1, lx, ly, lz);
+                if (i + 1 < N)
+                    bead(i + 1, rx, ry, rz);
+                double ax, ay, az, cx, cy, cz;
+                if (i > 0 && i < N - 1) { // about the line through both neighbours
+                    ax = (double)rx - (double)lx;
+                    ay = (double)ry - (double)ly;
+                    az = (double)rz - (double)lz;
+                    cx = lx, cy = ly, cz = lz;
+                } else { // an end bead: about a coordinate axis through its neighbour
+                    const uint32_t axis = (uint32_t)(((uint64_t)w.w[1] * 3u) >> 32);
+                    ax = axis == 0u ? 1.0 : 0.0;
+                    ay = axis == 1u ? 1.0 : 0.0;
+                    az = axis == 2u ? 1.0 : 0.0;
+                    cx = i == 0 ? rx : lx, cy = i == 0 ? ry : ly, cz = i == 0 ? rz : lz;
+                }
+                double ox, oy, oz;
+                quat_rotate(rot_tau(w.w[0]), ax, ay, az, (double)xi - cx, (double)yi - cy, (double)zi - cz, ox, oy,
+                            oz);
+                const float nx = (float)(cx + ox), ny = (float)(cy + oy), nz = (float)(cz + oz);
+                bool brl = false, brr = false;
+                const double fl = i >= 1 ? fene_energy(p, dist2(lx, ly, lz, nx, ny, nz), &brl) : 0.0;
+                const double fr = i + 1 < N ? fene_energy(p, dist2(rx, ry, rz, nx, ny, nz), &brr) : 0.0;
+                const double ub_i = bond_of(i);
+                double t = 0.0;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const int bd = j + 64 * s;
+                    const int sep = bd > i ? bd - i : i - bd;
+                    double ts = 0.0;
+                    if (bd < N && sep >= 2) {
+                        const double r2n = dist2(x[s].x, x[s].y, x[s].z, nx, ny, nz);
+                        const double r2o = dist2(x[s].x, x[s].y, x[s].z, xi, yi, zi);
+                        ts = lj_energy(p, r2n) - lj_energy(p, r2o);
+                    }
+                    if (bd == i + 1)
+                        ts = fr - ub_i;
+                    if (bd == i - 1)
+                        ts = fl - ub[s];
+                    t = s == 0 ? ts : t + ts;
+                }
+                const double dE = readlane_f64(tree_sum(t), 0);
+                const double En = E + dE;
+                const int32_t bn = energy_bin(p, En, a.n_bins);
+                bool acc = false;
+                if (!brl && !brr && bn >= 0)
+                    acc = min(w.w[3], 0xFFFFFFFEu) < a.thresholds[(size_t)b * B + (uint32_t)bn];
+                if (acc) {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        const int bd = j + 64 * s;
+                        if (bd == i) {
+                            x[s].x = nx;
+                            x[s].y = ny;
+                            x[s].z = nz;
+                            if (i + 1 < N)
+                                ub[s] = fr;
+                        }
+                        if (bd == i - 1)
+                            ub[s] = fl;
+                    }
+                    E = En;
+                    b = bn;
+                }
+            }
+            // one double bridging: bonds (bi, bi+1), (bj, bj+1) -> (bi, bj), (bi+1, bj+1)
+            const Words4 w = philox4x32_10(chain, g, 0u, kTagBridge, a.k0, a.k1);
+            int bi = (int)(((uint64_t)w.w[0] * (uint64_t)(N - 1)) >> 32);
+            int bj = (int)(((uint64_t)w.w[1] * (uint64_t)(N - 1)) >> 32);
+            if (bi > bj) {
+                const int tmp = bi;
+                bi = bj;
+                bj = tmp;
+            }
+            if (N >= 4 && bj - bi >= 2) {
+                float ix, iy, iz, kx, ky, kz, jx, jy, jz, mx, my, mz; // beads bi, bi+1, bj, bj+1
+                bead(bi, ix, iy, iz);
+                bead(bi + 1, kx, ky, kz);
+                bead(bj, jx, jy, jz);
+                bead(bj + 1, mx, my, mz);
+                bool br = false;
+                const double fij = fene_energy(p, dist2(ix, iy, iz, jx, jy, jz), &br);
+                const double fkl = fene_energy(p, dist2(kx, ky, kz, mx, my, mz), &br);
+                if (!br) {
+                    const double fik = bond_of(bi), fjl = bond_of(bj);
+                    const double lij = lj_energy(p, dist2(ix, iy, iz, jx, jy, jz));
+                    const double lkl = lj_energy(p, dist2(kx, ky, kz, mx, my, mz));
+                    const double lik = lj_energy(p, dist2(ix, iy, iz, kx, ky, kz));
+                    const double ljl = lj_energy(p, dist2(jx, jy, jz, mx, my, mz));
+                    const double dF = ((fij + fkl) - fik) - fjl;
+                    const double dL = ((lik + ljl) - lij) - lkl;
+                    const double En = E + (dF + dL);
+                    const int32_t bn = energy_bin(p, En, a.n_bins);
+                    if (bn >= 0 && min(w.w[3], 0xFFFFFFFEu) < a.thresholds[(size_t)b * B + (uint32_t)bn]) {
+                        // beads bi+1 .. bj in reverse order; the bonds between them reversed
+                        float4 nxs[NS];
+                        double nub[NS];
+#pragma unroll
+                        for (int s = 0; s < NS; ++s) {
+                            const int bd = j + 64 * s;
+                            const int sx = (bd > bi && bd <= bj) ? bi + 1 + bj - bd : bd;
+                            const int su = (bd > bi && bd < bj) ? bi + bj - bd : bd;
+                            float4 v0, v1 = make_float4(0.f, 0.f, 0.f, 0.f);
+                            v0.x = from_lane(x[0].x, sx & 63), v0.y = from_lane(x[0].y, sx & 63);
+                            v0.z = from_lane(x[0].z, sx & 63), v0.w = 0.f;
+                            double u0 = from_lane_f64(ub[0], su & 63), u1 = 0.0;
+                            if constexpr (TWO) {
+                                v1.x = from_lane(x[NS - 1].x, sx & 63), v1.y = from_lane(x[NS - 1].y, sx & 63);
+                                v1.z = from_lane(x[NS - 1].z, sx & 63);
+                                u1 = from_lane_f64(ub[NS - 1], su & 63);
+                            }
+                            nxs[s] = sx >= 64 ? v1 : v0;
+                            nub[s] = su >= 64 ? u1 : u0;
+                            if (bd == bi)
+                                nub[s] = fij;
+                            if (bd == bj)
+                                nub[s] = fkl;
+                        }
+#pragma unroll
+                        for (int s = 0; s < NS; ++s) {
+                            x[s] = nxs[s];
+                            ub[s] = nub[s];
+                        }
+                        E = En;
+                        b = bn;
+                    }
+                }
+            }
         }
         if (counts)
             atomicAdd(&lhist[b], 1u);

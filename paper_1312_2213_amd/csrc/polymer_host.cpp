@@ -40,6 +40,8 @@ int muca_polymer_geometry(const muca_config *c, Geometry *g)
 {
     if (c->n_beads < 2 || c->n_beads > 128)
         return muca_fail(MUCA_E_ARG, "n_beads %d outside 2..128", c->n_beads);
+    if (c->moves != 0 && c->moves != 1)
+        return muca_fail(MUCA_E_ARG, "moves %d: 0 (shifts) or 1 (shifts, rotations, double bridging)", c->moves);
     if (c->n_bins < 2 || c->n_bins > 8192 || !(c->x_hi > c->x_lo))
         return muca_fail(MUCA_E_ARG, "bad energy binning (%d bins on [%g, %g))", c->n_bins, c->x_lo, c->x_hi);
     if (!(c->fene_R > 0.0) || !(c->lj_rcut > 0.0) || !(c->lj_sigma > 0.0) || !(c->step > 0.0f))
@@ -229,6 +231,7 @@ int muca_polymer_enqueue(muca_run *r, int64_t sweeps, bool record, hipStream_t s
         a.chains_per_block = g.cpb;
         a.chain0 = r->cfg.chain0;
         a.step = r->cfg.step;
+        a.moves = r->cfg.moves;
         hipError_t e = launch_polymer_sweeps(a, k, s);
         if (e != hipSuccess) {
             r->poisoned = true;

@@ -77,6 +77,8 @@ int muca_geometry(const muca_config *c, Geometry *g)
         return muca_polymer_geometry(c, g);
     if (c->model != kIsing && c->model != kPotts && c->model != kMuma)
         return muca_fail(MUCA_E_ARG, "unknown model %d", c->model);
+    if (c->moves != 0)
+        return muca_fail(MUCA_E_ARG, "moves %d: the move set is a polymer option", c->moves);
     if (!lattice_size_supported(c->L))
         return muca_fail(MUCA_E_ARG, "L = %d not compiled (4, 8, 16, 24, 32, 48, 64)", c->L);
     const int N = c->L * c->L;

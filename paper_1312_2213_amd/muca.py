@@ -20,7 +20,7 @@ _LIB_PATH = os.path.join(_HERE, "libmuca.so")
 
 MUCA_ISING, MUCA_POTTS, MUCA_MUMA, MUCA_POLYMER = 0, 1, 2, 3
 MUCA_LAYOUT_AUTO, MUCA_LAYOUT_BIT, MUCA_LAYOUT_BYTE = 0, 1, 2
-MUCA_ABI_VERSION = 2
+MUCA_ABI_VERSION = 3
 MODELS = {"ising": MUCA_ISING, "potts": MUCA_POTTS, "muma": MUCA_MUMA, "polymer": MUCA_POLYMER}
 
 
@@ -40,7 +40,8 @@ class muca_config(ctypes.Structure):
                 ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double),
                 ("lj_eps", ctypes.c_double), ("lj_sigma", ctypes.c_double), ("lj_rcut", ctypes.c_double),
                 ("fene_k", ctypes.c_double), ("fene_r0", ctypes.c_double), ("fene_R", ctypes.c_double),
-                ("step", ctypes.c_float), ("lanes_per_chain", ctypes.c_int32), ("chain0", ctypes.c_int32)]
+                ("step", ctypes.c_float), ("lanes_per_chain", ctypes.c_int32), ("chain0", ctypes.c_int32),
+                ("moves", ctypes.c_int32)]
 
 
 class muca_iter_stats(ctypes.Structure):

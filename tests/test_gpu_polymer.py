@@ -73,9 +73,10 @@ def test_polymer_full_size_sampled():
     check_state(o, g, chains=(0, 1, 63, 64, 2048, 4095))
 
 
-def pair_paper(n_beads, chains, seed, lnw_slope=None):
+def pair_paper(n_beads, chains, seed, lnw_slope=None, moves=0):
     """The paper's homopolymer (Eq. 7 with its K, r0, r_max; sigma = 2^(-1/6)
-    r0; no LJ cutoff); 1000 bins of 0.5 on [-400, 100)."""
+    r0; no LJ cutoff); 1000 bins of 0.5 on [-400, 100); moves = 1 adds the
+    paper's spherical rotations and double bridging to the shifts."""
     import torch  # noqa: F401
     from oracle import oracle as orc
     from paper_1312_2213_amd import muca
@@ -83,8 +84,8 @@ def pair_paper(n_beads, chains, seed, lnw_slope=None):
     pp = dict(PAPER_POLYMER)
     rng = dict(x_lo=-400.0, x_hi=100.0, n_bins=1000)
     pos = polymer_walk(n_beads, chains, seed, bond=pp["fene_r0"], min_dist=pp["lj_sigma"])
-    o = orc.PolymerRun(n_beads=n_beads, n_chains=chains, seed=seed, pos=pos, **rng, **pp)
-    cfg = muca.muca_config_default("polymer", 0, 2, chains, seed, n_beads=n_beads, **rng, **pp)
+    o = orc.PolymerRun(n_beads=n_beads, n_chains=chains, seed=seed, pos=pos, moves=moves, **rng, **pp)
+    cfg = muca.muca_config_default("polymer", 0, 2, chains, seed, n_beads=n_beads, moves=moves, **rng, **pp)
     g = muca.Run(cfg, positions=pos)
     if lnw_slope is not None:
         lnw = lnw_slope * o.bin_centres()
@@ -121,3 +122,30 @@ def test_paper_polymer_iterations_with_recursion():
         assert np.array_equal(g.last_hist(), H), it
         assert np.allclose(g.lnw(), o.lnW, rtol=0, atol=1e-12), it
     check_state(o, g)
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 40, 64, 80, 128])
+def test_paper_move_set(N):
+    """Shifts, spherical rotations and double bridging (the paper's move
+    set): identical histograms, bins, float positions; N = 80 and 128 take
+    the two-beads-per-lane kernel, whose bridging permutes across both bead
+    sets; the weights favour compact conformations so bridging is accepted."""
+    print(f"paper polymer, full move set, N={N}", flush=True)
+    o, g = pair_paper(N, 65, 40 + N, lnw_slope=-1.5, moves=1)
+    for it in range(2):
+        H = o.sweeps(10)
+        o.advance(10)
+        o.merge_update(H)
+        g.run_iteration(10)
+        g.merge_update()
+        assert np.array_equal(g.last_hist(), H), it
+        assert np.allclose(g.lnw(), o.lnW, rtol=0, atol=1e-12), it
+    check_state(o, g)
+
+
+def test_move_set_is_refused_for_lattices():
+    from paper_1312_2213_amd import muca
+    cfg = muca.muca_config_default("ising", 8, 2, 16, 1, moves=1)
+    with pytest.raises(muca.MucaError):
+        muca.Run(cfg)
+
