@@ -65,8 +65,9 @@ def parse():
                     help="iteration cap (default: 40 batched, 3000 serving, 1000 speedup)")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--systems", default="", help="speedup: comma-separated indices of the systems to run")
-    ap.add_argument("--speedup-set", default="paper", choices=["paper", "qscan"],
-                    help="speedup: the paper's spin systems, or the q-state Potts crossover scan")
+    ap.add_argument("--speedup-set", default="paper", choices=["paper", "qscan", "polymer"],
+                    help="speedup: the paper's spin systems, the q-state Potts crossover scan, or the "
+                         "paper's homopolymer")
     ap.add_argument("--qscan-L", type=int, default=16, help="speedup --speedup-set qscan: lattice size")
     ap.add_argument("--round-site-updates", type=int, default=1 << 16,
                     help="serving: site updates per chain in one round")
@@ -419,6 +420,21 @@ def bench_speedup(args):
     """Statistical speedup S*_p (Eq. 6) of the paper's systems: one JSON line
     per system with N_iter to flat and to full coverage per p."""
     from paper_1312_2213_amd import speedup as su
+    if args.speedup_set == "polymer":
+        systems = su.paper_polymer_systems()
+        if args.systems:
+            systems = [systems[int(k)] for k in args.systems.split(",")]
+        for system, ps, replicas in systems:
+            print(f"== {system.name}: p = {ps}, {replicas} runs each", file=sys.stderr, flush=True)
+            res = su.run_polymer(system, ps, replicas, seed0=1, max_iters=args.max_iters,
+                                 log=lambda m: print(m, file=sys.stderr, flush=True))
+            print(json.dumps({"metric": "statistical speedup S*_p (iterations to flat at equal statistics)",
+                              "system": system.name, "n_beads": system.n_beads, "window": [system.lo, system.hi],
+                              "n_bins": system.n_bins, "sweeps_total": system.sweeps_total,
+                              "therm_frac": system.therm_frac, "replicas": replicas, "max_iters": args.max_iters,
+                              "seconds": res.seconds, "flat": res.table("n_iter"), "cover": res.table("n_cover"),
+                              "n_iter": {str(p): v for p, v in res.n_iter.items()}}), flush=True)
+        return None
     systems = su.paper_systems() if args.speedup_set == "paper" else su.q_scan_systems(args.qscan_L)
     if args.systems:
         systems = [systems[int(k)] for k in args.systems.split(",")]

@@ -186,3 +186,145 @@ def q_scan_systems(L: int = 16, qs=range(2, 11), ps=None, replicas: int = 8) -> 
     ps = list(ps) if ps is not None else [2 ** k for k in range(4, 12)]
     return [(System("potts", L, q=q, potts_law=q >= 3), ps, replicas) for q in qs]
 
+
+# --------------------------------------------------------------------------
+# The bead-spring homopolymer (the paper's polymer figure)
+# --------------------------------------------------------------------------
+@dataclass
+class PolymerSystem:
+    """The paper's homopolymer (Eq. 7 with its parameters) with the paper's
+    move set, its energy range restricted to a window around the collapse
+    transition, a fixed number of sweeps per iteration summed over the p
+    chains (M(p) = ceil(M_total / p)), and thermalisation sweeps before
+    every iteration (a fraction of M(p), at least one)."""
+    n_beads: int
+    lo: float
+    hi: float
+    n_bins: int
+    sweeps_total: int
+    therm_frac: float = 0.25
+    moves: int = 1
+
+    def sweeps(self, p: int) -> int:
+        return max(1, math.ceil(self.sweeps_total / p))
+
+    def therm(self, p: int) -> int:
+        return max(1, math.ceil(self.therm_frac * self.sweeps(p)))
+
+    def config(self, p: int, seed: int):
+        from synth import PAPER_POLYMER
+        return muca.muca_config_default("polymer", 0, 2, p, seed, n_beads=self.n_beads, x_lo=self.lo,
+                                        x_hi=self.hi, n_bins=self.n_bins, moves=self.moves, **PAPER_POLYMER)
+
+    @property
+    def name(self) -> str:
+        return f"homopolymer N={self.n_beads} E in [{self.lo:g}, {self.hi:g})"
+
+
+def polymer_flatness(H) -> float:
+    """min / mean over every bin of the window (all are reachable there)."""
+    H = np.asarray(H, np.float64)
+    return float(H.min() / H.mean()) if H.sum() > 0 else 0.0
+
+
+def polymer_start(system: PolymerSystem, count: int, seed: int = 99, chains: int = 4096,
+                  wide=(-220.0, 40.0, 520), max_iters: int = 400, stream=None) -> np.ndarray:
+    """`count` conformations [count][N][3] whose energies lie in the window:
+    a multicanonical run over a wide range from random walks, collecting the
+    chains inside the window after each iteration (each chain at most once
+    per iteration)."""
+    from synth import PAPER_POLYMER, polymer_walk
+    pp = dict(PAPER_POLYMER)
+    pos = polymer_walk(system.n_beads, chains, seed, bond=pp["fene_r0"], min_dist=pp["lj_sigma"])
+    cfg = muca.muca_config_default("polymer", 0, 2, chains, seed, n_beads=system.n_beads, x_lo=wide[0],
+                                   x_hi=wide[1], n_bins=wide[2], moves=system.moves, **pp)
+    run = muca.Run(cfg, positions=pos, stream=stream)
+    got = []
+    n = 0
+    for _ in range(max_iters):
+        run.run_iteration(200)
+        run.merge_update()
+        state, _, E = run.chain_state()
+        sel = (E >= system.lo) & (E < system.hi)
+        got.append(state[sel])
+        n += int(sel.sum())
+        if n >= count:
+            break
+    run.free()
+    if n < count:
+        raise RuntimeError(f"only {n} conformations in the window after {max_iters} iterations")
+    return np.concatenate(got)[:count]
+
+
+def run_polymer(system: PolymerSystem, ps: list[int], replicas: int, seed0: int = 1, max_iters: int = 500,
+                start: np.ndarray | None = None, n_streams: int = 4, log=None) -> Result:
+    """S*_p of the homopolymer: `replicas` runs per p, each from lnW = 0
+    with distinct start conformations (from the window) and seeds, all runs
+    advancing together (one iteration each per round, spread over a few
+    streams), every run retiring at its first flat iteration."""
+    import time
+
+    import torch
+    total = sum(ps) * replicas
+    if start is None:
+        start = polymer_start(system, total)
+    if len(start) < total:
+        raise ValueError(f"need {total} start conformations, got {len(start)}")
+    streams = [torch.cuda.Stream() for _ in range(n_streams)]
+    sweeps = [system.sweeps(p) for p in ps]
+    specs, runs, off = [], [], 0
+    for k, p in enumerate(ps):
+        for r in range(replicas):
+            st = streams[len(runs) % n_streams]
+            runs.append(muca.Run(system.config(p, seed_of(seed0, k, r)), positions=start[off:off + p], stream=st))
+            specs.append((p, r, st))
+            off += p
+    res = Result(system.name, list(ps), sweeps, {p: [None] * replicas for p in ps},
+                 {p: [None] * replicas for p in ps}, {p: [[] for _ in range(replicas)] for p in ps})
+    live = list(range(len(runs)))
+    n = [0] * len(runs)
+    t0 = time.perf_counter()
+    rounds = 0
+    while live:
+        rounds += 1
+        if log and rounds % 50 == 0:
+            log(f"{system.name}: round {rounds}, {len(live)} runs live, {time.perf_counter() - t0:.1f} s")
+        for i in live:
+            p, _, st = specs[i]
+            runs[i].thermalize(system.therm(p), stream=st)
+            runs[i].run_iteration(system.sweeps(p), stream=st)
+        nxt = []
+        for i in live:
+            p, r, _ = specs[i]
+            runs[i].merge_update()
+            H = runs[i].last_hist()
+            f = polymer_flatness(H)
+            n[i] += 1
+            res.trace[p][r].append(f)
+            if f > 0 and res.n_cover[p][r] is None:
+                res.n_cover[p][r] = n[i]
+            if f > 0.5 or n[i] >= max_iters:
+                res.n_iter[p][r] = n[i] if f > 0.5 else None
+                runs[i].free()
+                if log:
+                    log(f"{system.name} p={p} run {r}: {n[i]} iterations{'' if f > 0.5 else ' (capped)'}")
+            else:
+                nxt.append(i)
+        live = nxt
+    torch.cuda.synchronize()
+    res.seconds = time.perf_counter() - t0
+    return res
+
+
+def paper_polymer_systems() -> list[tuple[PolymerSystem, list[int], int]]:
+    """The paper's polymer figure (N = 40 and 80): windows around the
+    collapse transition where the canonical energy rises steeply (T between
+    about 0.9 and 1.8 for the paper's parameters, measured with this
+    library), bins 2 wide, 1024 sweeps per iteration in total: (system, p
+    values, replicas)."""
+    pw = [2 ** k for k in range(0, 9)]
+    return [
+        (PolymerSystem(40, -70.0, -20.0, 25, 1024), pw, 8),
+        (PolymerSystem(80, -140.0, -40.0, 50, 1024), pw[:8], 4),
+    ]
+

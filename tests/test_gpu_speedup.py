@@ -50,3 +50,35 @@ def test_iterations_to_flat_equal_the_oracle(spec):
     assert all(row["runs"] == replicas for row in rows)
     ref = [row for row in rows if row["speedup"] is not None]
     assert not ref or ref[0]["speedup"] == 1.0
+
+
+def test_polymer_driver_equals_the_oracle():
+    """The homopolymer speedup driver (thermalisation, then an iteration of
+    M(p) sweeps, per round; flatness over the whole window) against the
+    oracle run the same way from the same start conformations and seeds."""
+    from oracle import oracle as orc
+    from paper_1312_2213_amd import speedup as su
+    from synth import PAPER_POLYMER, polymer_walk
+    pp = dict(PAPER_POLYMER)
+    system = su.PolymerSystem(8, -30.0, 30.0, 60, 64)
+    ps, replicas, max_iters = [1, 4], 2, 6
+    start = polymer_walk(8, sum(ps) * replicas, 3, bond=pp["fene_r0"], min_dist=pp["lj_sigma"])
+    res = su.run_polymer(system, ps, replicas, seed0=5, max_iters=max_iters, start=start)
+    off = 0
+    for k, p in enumerate(ps):
+        for r in range(replicas):
+            o = orc.PolymerRun(n_beads=8, n_chains=p, seed=su.seed_of(5, k, r), pos=start[off:off + p], moves=1,
+                               x_lo=system.lo, x_hi=system.hi, n_bins=system.n_bins, **pp)
+            off += p
+            trace = []
+            for _ in range(max_iters):
+                o.sweeps(system.therm(p), record=False)
+                o.advance(system.therm(p))
+                H = o.sweeps(system.sweeps(p))
+                o.advance(system.sweeps(p))
+                o.merge_update(H)
+                trace.append(su.polymer_flatness(H))
+                if trace[-1] > 0.5:
+                    break
+            assert res.trace[p][r] == trace, (p, r)
+

@@ -70,3 +70,13 @@ def test_q_scan_laws_and_grid():
     assert sc[0][0].sweeps(16) == math.ceil(5.7 * 16 ** 2.51 / 16)
     assert sc[6][0].sweeps(16) == math.ceil(24 * 16 ** 2.67 / 16)
 
+
+def test_polymer_system_sweeps_and_flatness():
+    s = su.PolymerSystem(40, -70.0, -20.0, 100, 1024)
+    assert [s.sweeps(p) for p in (1, 2, 3, 1024, 4096)] == [1024, 512, 342, 1, 1]
+    assert [s.therm(p) for p in (1, 8, 4096)] == [256, 32, 1]
+    assert su.polymer_flatness([4, 2, 6]) == pytest.approx(0.5)
+    assert su.polymer_flatness([0, 0]) == 0.0
+    (s40, ps, r), (s80, _, _) = su.paper_polymer_systems()
+    assert s40.n_beads == 40 and s80.n_beads == 80 and ps[0] == 1 and s40.moves == 1
+
