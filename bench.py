@@ -65,7 +65,7 @@ def parse():
                     help="iteration cap (default: 40 batched, 3000 serving, 1000 speedup)")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--systems", default="", help="speedup: comma-separated indices of the systems to run")
-    ap.add_argument("--speedup-set", default="paper", choices=["paper", "qscan", "polymer"],
+    ap.add_argument("--speedup-set", default="paper", choices=["paper", "qscan", "polymer", "time"],
                     help="speedup: the paper's spin systems, the q-state Potts crossover scan, or the "
                          "paper's homopolymer")
     ap.add_argument("--qscan-L", type=int, default=16, help="speedup --speedup-set qscan: lattice size")
@@ -434,6 +434,19 @@ def bench_speedup(args):
                               "therm_frac": system.therm_frac, "replicas": replicas, "max_iters": args.max_iters,
                               "seconds": res.seconds, "flat": res.table("n_iter"), "cover": res.table("n_cover"),
                               "n_iter": {str(p): v for p, v in res.n_iter.items()}}), flush=True)
+        return None
+    if args.speedup_set == "time":
+        systems = su.time_systems()
+        if args.systems:
+            systems = [systems[int(k)] for k in args.systems.split(",")]
+        for system, ps, replicas in systems:
+            print(f"== {system.name}: p = {ps}, {replicas} runs each, alone", file=sys.stderr, flush=True)
+            res = su.run_alone(system, ps, replicas, seed0=1, max_iters=args.max_iters,
+                               log=lambda m: print(m, file=sys.stderr, flush=True))
+            print(json.dumps({"metric": "time speedup S_p = t_1 / t_p (wall time to flat, each run alone)",
+                              "system": system.name, "replicas": replicas, "max_iters": args.max_iters,
+                              "seconds": res.seconds, "time": su.time_speedup(res), "flat": res.table("n_iter")}),
+                  flush=True)
         return None
     systems = su.paper_systems() if args.speedup_set == "paper" else su.q_scan_systems(args.qscan_L)
     if args.systems:

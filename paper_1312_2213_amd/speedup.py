@@ -157,6 +157,80 @@ def run(system: System, ps: list[int], replicas: int, seed0: int = 1, flat: floa
     return res
 
 
+def run_alone(system: System, ps: list[int], replicas: int, seed0: int = 1, flat: float = 0.5,
+              max_iters: int = 1000, log=None) -> Result:
+    """The time speedup of Eq. 5 on one GPU: every (p, replica) run alone
+    (nothing else on the device), one plain launch per iteration followed by
+    the merge; t_p = wall time from the first launch to the merged flat
+    histogram (launches, histogram download, recursion and threshold upload
+    included: the on-device counterpart of the paper's per-iteration
+    communication).  Same seeds as `run`, so the same chains and N_iter.
+    Result.seconds_per_run[p] holds the times of the replicas."""
+    import time
+
+    import torch
+    stream = torch.cuda.Stream()
+    sweeps = [system.sweeps(p) for p in ps]
+    res = Result(system.name, list(ps), sweeps, {p: [None] * replicas for p in ps},
+                 {p: [None] * replicas for p in ps}, {p: [[] for _ in range(replicas)] for p in ps})
+    res.seconds_per_run = {p: [None] * replicas for p in ps}
+    t_all = time.perf_counter()
+    for k, (p, m) in enumerate(zip(ps, sweeps)):
+        for r in range(replicas):
+            with torch.cuda.stream(stream):
+                run = muca.Run(system.config(p, seed_of(seed0, k, r), flat), stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n, st = 0, None
+            while n < max_iters:
+                run.run_iteration(m)
+                st = run.merge_update()
+                n += 1
+                res.trace[p][r].append(st["flatness"])
+                if st["flatness"] > 0 and res.n_cover[p][r] is None:
+                    res.n_cover[p][r] = n
+                if st["flat"]:
+                    break
+            dt = time.perf_counter() - t0
+            res.n_iter[p][r] = n if st["flat"] else None
+            res.seconds_per_run[p][r] = dt if st["flat"] else None
+            run.free()
+            if log:
+                log(f"{system.name} p={p} seed={seed_of(seed0, k, r)} alone: {n} iterations, {dt:.3f} s"
+                    f"{'' if st['flat'] else ' (capped)'}")
+    res.seconds = time.perf_counter() - t_all
+    return res
+
+
+def time_speedup(res: Result) -> list[dict]:
+    """S_p = t_p0 / t_p (Eq. 5, relative to the smallest fully converged p)
+    with the mean wall time to flat per p and its standard error."""
+    rows = []
+    for p, m in zip(res.ps, res.sweeps):
+        v = [x for x in res.seconds_per_run[p] if x is not None]
+        mean = float(np.mean(v)) if v else None
+        err = float(np.std(v, ddof=1) / math.sqrt(len(v))) if len(v) > 1 else None
+        rows.append({"p": p, "sweeps_per_iteration": m, "runs": len(res.seconds_per_run[p]),
+                     "capped": len(res.seconds_per_run[p]) - len(v), "t_mean_s": mean, "t_err_s": err,
+                     "S_p": None, "S_p_err": None})
+    base = next((r for r in rows if r["capped"] == 0 and r["t_err_s"] is not None), None)
+    if base is not None:
+        for r in rows[rows.index(base):]:
+            if r["t_mean_s"] is not None and r["t_err_s"] is not None:
+                s = base["t_mean_s"] / r["t_mean_s"]
+                rel = math.sqrt((base["t_err_s"] / base["t_mean_s"]) ** 2 + (r["t_err_s"] / r["t_mean_s"]) ** 2)
+                r["S_p"], r["S_p_err"] = s, s * rel
+    return rows
+
+
+def time_systems() -> list[tuple[System, list[int], int]]:
+    """Systems of the time-speedup measurement: the 8-state Potts model at
+    L = 8 (converges from p = 1) and the Ising model at L = 16 (from p = 4,
+    see the remark on lnW = 0 above)."""
+    pw = [2 ** k for k in range(0, 11)]
+    return [(System("potts", 8, q=8, potts_law=True), pw, 8), (System("ising", 16), pw[2:], 8)]
+
+
 def paper_systems() -> list[tuple[System, list[int], int]]:
     """The systems of the paper's speedup figures (Ising; 8-state Potts with
     its own power law; multimagnetic Ising at T = 2/3 T_c with the Ising

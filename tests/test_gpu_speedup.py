@@ -82,3 +82,20 @@ def test_polymer_driver_equals_the_oracle():
                     break
             assert res.trace[p][r] == trace, (p, r)
 
+
+def test_runs_alone_take_the_batched_iteration_counts():
+    """Each run alone (the time-speedup measurement) is the same chain as in
+    the batched driver: identical flatness traces and N_iter; the wall
+    times are recorded for the flat runs."""
+    from paper_1312_2213_amd import speedup as su
+    system = su.System("potts", 8, q=5, potts_law=True)
+    ps, replicas = [2, 8, 32], 2
+    alone = su.run_alone(system, ps, replicas, seed0=3, max_iters=200)
+    batched = su.run(system, ps, replicas, seed0=3, max_iters=200)
+    for p in ps:
+        assert alone.trace[p] == batched.trace[p] and alone.n_iter[p] == batched.n_iter[p]
+        for t, n in zip(alone.seconds_per_run[p], alone.n_iter[p]):
+            assert (t is None) == (n is None) and (t is None or t > 0)
+    rows = su.time_speedup(alone)
+    assert [r["p"] for r in rows] == ps
+

@@ -80,3 +80,11 @@ def test_polymer_system_sweeps_and_flatness():
     (s40, ps, r), (s80, _, _) = su.paper_polymer_systems()
     assert s40.n_beads == 40 and s80.n_beads == 80 and ps[0] == 1 and s40.moves == 1
 
+
+def test_time_speedup_table():
+    r = su.Result("x", [1, 4], [100, 25], {1: [10, 10], 4: [10, 10]}, {1: [1, 1], 4: [1, 1]})
+    r.seconds_per_run = {1: [2.0, 2.2], 4: [0.5, 0.6]}
+    rows = su.time_speedup(r)
+    assert rows[0]["S_p"] == 1.0
+    assert rows[1]["S_p"] == pytest.approx(2.1 / 0.55)
+
