@@ -32,6 +32,6 @@ WORKLOADS = {
 # The paper's bead-spring homopolymer (Eq. 7 and the parameters stated with
 # it): FENE K = 40, r0 = 0.7, r_max = 1 (R = 0.3); Lennard-Jones with
 # sigma = 2^(-1/6) r0 (its minimum at r0) and no cutoff; N = 40 and 80.
-# The displacement cube side (0.3 sigma) is this build's choice.
+# The displacement cube side (0.3 sigma) is not stated in the paper: a choice here.
 PAPER_POLYMER = dict(lj_eps=1.0, lj_sigma=2.0 ** (-1.0 / 6.0) * 0.7, lj_rcut=math.inf,
                      fene_k=40.0, fene_r0=0.7, fene_R=0.3, step=0.3 * 2.0 ** (-1.0 / 6.0) * 0.7)

@@ -1,4 +1,4 @@
-"""Pins the exact references that the oracle is judged against: brute force,
+"""Pins the exact references that the oracle is checked against: brute force,
 transfer matrix and Kaufman's closed form must agree, and must reproduce the
 low-temperature counts that follow from counting clusters by hand."""
 import math
