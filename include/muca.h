@@ -108,6 +108,10 @@ typedef struct muca_iter_stats {
     int32_t lo_visited; /* lowest / highest bin with H^(n) > 0, -1 if none     */
     int32_t hi_visited;
     int32_t reserved;
+    double accept_rate; /* accepted / attempted moves over the sweeps of H^(n)
+                           (lattice: N attempts per chain and sweep; polymer:
+                           N, or 2N + 1 with the full move set); a sharded
+                           run reports its own chains                        */
 } muca_iter_stats;
 
 typedef struct muca_run muca_run;

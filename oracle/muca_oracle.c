@@ -284,7 +284,7 @@ static int accept(uint32_t T, uint32_t r)
  * sweep the chain's bin is added to H if record != 0.  E and M are carried. */
 static int sweeps_impl(const orc_lattice *c, int8_t *spins, int32_t *E, int32_t *M,
                        const uint32_t *T, uint32_t g0, int64_t n_sweeps, int record,
-                       uint64_t *H, uint64_t *HEM, int32_t ch_lo, int32_t ch_hi)
+                       uint64_t *H, uint64_t *HEM, uint64_t *ACC, int32_t ch_lo, int32_t ch_hi)
 {
     int32_t L = c->L, N = L * L, nc = orc_ncols(c->model), B = orc_nbins(c);
     int32_t step = bin_step(c->model), ch;
@@ -323,6 +323,8 @@ static int sweeps_impl(const orc_lattice *c, int8_t *spins, int32_t *E, int32_t 
                     if (accept(T[b * nc + (dE + 4)], wa)) {
                         s[i] = (int8_t)nw;
                         E[ch] += dE;
+                        if (record && ACC)
+                            *ACC += 1u;
                     }
                 } else {
                     uint32_t r;
@@ -338,6 +340,8 @@ static int sweeps_impl(const orc_lattice *c, int8_t *spins, int32_t *E, int32_t 
                             s[i] = (int8_t)(-s[i]);
                             E[ch] += dE;
                             M[ch] += 2 * s[i];
+                            if (record && ACC)
+                                *ACC += 1u;
                         }
                     } else {
                         b = (M[ch] - c->lo) / step;
@@ -345,6 +349,8 @@ static int sweeps_impl(const orc_lattice *c, int8_t *spins, int32_t *E, int32_t 
                             s[i] = (int8_t)(-s[i]);
                             E[ch] += dE;
                             M[ch] += 2 * s[i];
+                            if (record && ACC)
+                                *ACC += 1u;
                         }
                     }
                 }
@@ -370,7 +376,16 @@ int orc_sweeps(const orc_lattice *c, int8_t *spins, int32_t *E, int32_t *M,
                const uint32_t *T, uint32_t g0, int64_t n_sweeps, int record,
                uint64_t *H, int32_t ch_lo, int32_t ch_hi)
 {
-    return sweeps_impl(c, spins, E, M, T, g0, n_sweeps, record, H, NULL, ch_lo, ch_hi);
+    return sweeps_impl(c, spins, E, M, T, g0, n_sweeps, record, H, NULL, NULL, ch_lo, ch_hi);
+}
+
+/* orc_sweeps that also adds the number of accepted moves of the recorded
+ * sweeps to *ACC (the acceptance rate of an iteration). */
+int orc_sweeps_acc(const orc_lattice *c, int8_t *spins, int32_t *E, int32_t *M,
+                   const uint32_t *T, uint32_t g0, int64_t n_sweeps, int record,
+                   uint64_t *H, uint64_t *ACC, int32_t ch_lo, int32_t ch_hi)
+{
+    return sweeps_impl(c, spins, E, M, T, g0, n_sweeps, record, H, NULL, ACC, ch_lo, ch_hi);
 }
 
 /* orc_sweeps of a MUMA run that also counts every recorded sweep in
@@ -382,7 +397,7 @@ int orc_sweeps_em(const orc_lattice *c, int8_t *spins, int32_t *E, int32_t *M,
 {
     if (c->model != ORC_MUMA)
         return -2;
-    return sweeps_impl(c, spins, E, M, T, g0, n_sweeps, record, H, HEM, ch_lo, ch_hi);
+    return sweeps_impl(c, spins, E, M, T, g0, n_sweeps, record, H, HEM, NULL, ch_lo, ch_hi);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -865,9 +880,22 @@ static int polymer_accept(const orc_polymer *p, const double *lnW, double *E, in
 
 /* T2 is the B x B threshold matrix T2[b*B + b'] of lnW(b') - lnW(b); pass
  * NULL to evaluate the rule from lnW directly (same values). */
+int orc_polymer_sweeps_acc(const orc_polymer *p, float *pos, double *E, int32_t *bin,
+                           const double *lnW, uint32_t g0, int64_t n_sweeps, int record,
+                           uint64_t *H, uint64_t *ACC, int32_t ch_lo, int32_t ch_hi);
+
 int orc_polymer_sweeps(const orc_polymer *p, float *pos, double *E, int32_t *bin,
                        const double *lnW, uint32_t g0, int64_t n_sweeps, int record,
                        uint64_t *H, int32_t ch_lo, int32_t ch_hi)
+{
+    return orc_polymer_sweeps_acc(p, pos, E, bin, lnW, g0, n_sweeps, record, H, NULL, ch_lo, ch_hi);
+}
+
+/* orc_polymer_sweeps that also adds the accepted moves of the recorded
+ * sweeps to *ACC. */
+int orc_polymer_sweeps_acc(const orc_polymer *p, float *pos, double *E, int32_t *bin,
+                           const double *lnW, uint32_t g0, int64_t n_sweeps, int record,
+                           uint64_t *H, uint64_t *ACC, int32_t ch_lo, int32_t ch_hi)
 {
     int32_t ch, nb = p->n_beads;
     for (ch = ch_lo; ch < ch_hi; ++ch) {
@@ -901,6 +929,8 @@ int orc_polymer_sweeps(const orc_polymer *p, float *pos, double *E, int32_t *bin
                     x[3 * i + 2] = xn[2];
                     E[ch] = En;
                     bin[ch] = bn;
+                    if (record && ACC)
+                        *ACC += 1u;
                 }
             }
             if (p->moves) {
@@ -921,6 +951,8 @@ int orc_polymer_sweeps(const orc_polymer *p, float *pos, double *E, int32_t *bin
                         x[3 * i + 0] = xn[0];
                         x[3 * i + 1] = xn[1];
                         x[3 * i + 2] = xn[2];
+                        if (record && ACC)
+                            *ACC += 1u;
                     }
                 }
                 /* one double-bridging attempt */
@@ -929,6 +961,8 @@ int orc_polymer_sweeps(const orc_polymer *p, float *pos, double *E, int32_t *bin
                     draw(p->seed, (uint32_t)ch, g, 0u, ORC_TAG_BRIDGE, w);
                     if (bridging_proposal(p, x, w, &dEb, &bi, &bj) &&
                         polymer_accept(p, lnW, &E[ch], &bin[ch], dEb, w[3])) {
+                        if (record && ACC)
+                            *ACC += 1u;
                         for (i = bi + 1, k = bj; i < k; ++i, --k) {
                             int32_t d;
                             for (d = 0; d < 3; ++d) {

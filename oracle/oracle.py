@@ -85,6 +85,13 @@ def lib():
         L.orc_sweeps.argtypes = [P(_Lattice), i8p, i32p, i32p, u32p, ctypes.c_uint32,
                                  ctypes.c_int64, ctypes.c_int, u64p, ctypes.c_int32, ctypes.c_int32]
         L.orc_sweeps.restype = ctypes.c_int
+        L.orc_sweeps_acc.argtypes = [P(_Lattice), i8p, i32p, i32p, u32p, ctypes.c_uint32,
+                                     ctypes.c_int64, ctypes.c_int, u64p, u64p, ctypes.c_int32, ctypes.c_int32]
+        L.orc_sweeps_acc.restype = ctypes.c_int
+        L.orc_polymer_sweeps_acc.argtypes = [P(_Polymer), f32p, f64p, i32p, f64p, ctypes.c_uint32,
+                                             ctypes.c_int64, ctypes.c_int, u64p, u64p, ctypes.c_int32,
+                                             ctypes.c_int32]
+        L.orc_polymer_sweeps_acc.restype = ctypes.c_int
         L.orc_sweeps_em.argtypes = [P(_Lattice), i8p, i32p, i32p, u32p, ctypes.c_uint32,
                                     ctypes.c_int64, ctypes.c_int, u64p, u64p, ctypes.c_int32, ctypes.c_int32]
         L.orc_sweeps_em.restype = ctypes.c_int
@@ -196,6 +203,11 @@ class LatticeRun:
         self.lnR = np.zeros(B, np.float64)
         self.P = np.zeros(B, np.float64)
         self.H = np.zeros(B, np.uint64)
+        self.accepted = 0  # accepted moves of recorded sweeps since the last take_accepted()
+
+    def take_accepted(self) -> int:
+        n, self.accepted = self.accepted, 0
+        return n
 
     @property
     def n_bins(self) -> int:
@@ -230,10 +242,13 @@ class LatticeRun:
         c0, c1 = (0, self.n_chains) if chains is None else chains
         if H is None:
             H = np.zeros(self.n_bins, np.uint64)
-        rc = lib().orc_sweeps(ctypes.byref(self._c), _ptr(self.spins, ctypes.c_int8),
-                              _ptr(self.E, ctypes.c_int32), _ptr(self.M, ctypes.c_int32),
-                              _ptr(T, ctypes.c_uint32), ctypes.c_uint32(self.sweep & 0xffffffff),
-                              ctypes.c_int64(n), int(record), _ptr(H, ctypes.c_uint64), c0, c1)
+        acc = np.zeros(1, np.uint64)
+        rc = lib().orc_sweeps_acc(ctypes.byref(self._c), _ptr(self.spins, ctypes.c_int8),
+                                  _ptr(self.E, ctypes.c_int32), _ptr(self.M, ctypes.c_int32),
+                                  _ptr(T, ctypes.c_uint32), ctypes.c_uint32(self.sweep & 0xffffffff),
+                                  ctypes.c_int64(n), int(record), _ptr(H, ctypes.c_uint64),
+                                  _ptr(acc, ctypes.c_uint64), c0, c1)
+        self.accepted += int(acc[0])
         if rc != 0:
             raise RuntimeError("oracle chain left the binned range")
         return H
@@ -393,6 +408,7 @@ class PolymerRun:
         self.lnR = np.zeros(self.n_bins, np.float64)
         self.P = np.zeros(self.n_bins, np.float64)
         self.visited = np.zeros(self.n_bins, np.uint8)
+        self.accepted = 0
 
     def energy(self, pos_one) -> float:
         """Total energy of one conformation [bead][3] (any number of beads)."""
@@ -428,12 +444,18 @@ class PolymerRun:
         c0, c1 = (0, self.n_chains) if chains is None else chains
         if H is None:
             H = np.zeros(self.n_bins, np.uint64)
-        lib().orc_polymer_sweeps(ctypes.byref(self._c), _ptr(self.pos, ctypes.c_float),
-                                 _ptr(self.E, ctypes.c_double), _ptr(self.bin, ctypes.c_int32),
-                                 _ptr(self.lnW, ctypes.c_double),
-                                 ctypes.c_uint32(self.sweep & 0xffffffff), ctypes.c_int64(n),
-                                 int(record), _ptr(H, ctypes.c_uint64), c0, c1)
+        acc = np.zeros(1, np.uint64)
+        lib().orc_polymer_sweeps_acc(ctypes.byref(self._c), _ptr(self.pos, ctypes.c_float),
+                                     _ptr(self.E, ctypes.c_double), _ptr(self.bin, ctypes.c_int32),
+                                     _ptr(self.lnW, ctypes.c_double),
+                                     ctypes.c_uint32(self.sweep & 0xffffffff), ctypes.c_int64(n),
+                                     int(record), _ptr(H, ctypes.c_uint64), _ptr(acc, ctypes.c_uint64), c0, c1)
+        self.accepted += int(acc[0])
         return H
+
+    def take_accepted(self) -> int:
+        n, self.accepted = self.accepted, 0
+        return n
 
     def advance(self, n: int):
         self.sweep += n

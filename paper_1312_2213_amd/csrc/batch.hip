@@ -321,6 +321,7 @@ extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, in
         d.a.record = 1;
         d.a.table_in_lds = tlds ? 1 : 0;
         d.a.chain0 = r->cfg.chain0;
+        d.a.accepts = r->d_hist + r->g.n_bins;
         d.variant = variant_index(kind, li, tlds ? 1 : 0, lpc[i] == 16 ? 1 : 0);
         const double per_site = r->g.model == kPotts ? 2.0 : 1.0;
         const double cost = per_site * (double)r->g.n_sites * (double)sweeps[i];

@@ -418,7 +418,7 @@ template <int MODEL, int L, int LPC, bool TLDS>
 __device__ __forceinline__ void ising_lp_row(const uint32_t (&up)[Row1<L>::W], uint32_t (&cur)[Row1<L>::W],
                                              const uint32_t (&dn)[Row1<L>::W], int32_t &rowb,
                                              const uint32_t *__restrict__ T, uint32_t chain, uint32_t g, int y,
-                                             uint32_t j, uint32_t k0, uint32_t k1)
+                                             uint32_t j, uint32_t k0, uint32_t k1, uint32_t &nacc)
 {
     static_assert(L % 4 == 0 && L >= 4, "rows of whole Philox calls");
     constexpr int W = Row1<L>::W;
@@ -499,6 +499,9 @@ __device__ __forceinline__ void ising_lp_row(const uint32_t (&up)[Row1<L>::W], u
     for (int wi = 0; wi < W; ++wi)
         F[wi] = 0u;
     ilp_sites<MODEL, L, LPC, TLDS>(pk, dv2, dv1, first, rowb, F, T, std::make_integer_sequence<int, L>{});
+#pragma unroll
+    for (int wi = 0; wi < W; ++wi)
+        nacc += (uint32_t)__builtin_popcount(F[wi]);
     // the flips were shifted in from the low end, first site highest
 #pragma unroll
     for (int wi = 0; wi < W; ++wi) {
@@ -675,6 +678,40 @@ __device__ __forceinline__ void flush_hist(uint32_t *lhist, int hw, unsigned lon
 // (byte stores when segments are not word-aligned); a lane only reads back
 // bytes it wrote itself.
 // ---------------------------------------------------------------------------
+// Adds a lane's count of accepted moves (recorded sweeps of a real chain,
+// leader lane) to the run's counter and clears it; the counts stay below
+// 2^32 between two flushes (at most N per sweep, flushed with the 16-bit
+// LDS histogram).
+__device__ __forceinline__ void flush_accepts(const LatticeArgs &a, bool counts, uint32_t &nacc)
+{
+    if (counts && a.accepts && nacc)
+        atomicAdd(a.accepts, (unsigned long long)nacc);
+    nacc = 0u;
+}
+
+// Sites of a row that changed: bits of bit-packed rows, bytes of byte rows.
+template <int W>
+__device__ __forceinline__ uint32_t changed_bits(const uint32_t (&a)[W], const uint32_t (&b)[W])
+{
+    uint32_t n = 0u;
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        n += (uint32_t)__builtin_popcount(a[w] ^ b[w]);
+    return n;
+}
+
+template <int W>
+__device__ __forceinline__ uint32_t changed_bytes(const uint32_t (&a)[W], const uint32_t (&b)[W])
+{
+    uint32_t n = 0u;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint32_t x = a[w] ^ b[w];
+        n += (uint32_t)__builtin_popcount((((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u);
+    }
+    return n;
+}
+
 template <int L, int LPC>
 struct PottsLP {
     static constexpr bool ok = (LPC == 4 || LPC == 16) && L % LPC == 0;
@@ -873,6 +910,7 @@ __device__ __forceinline__ int32_t potts_lp_sweeps(const LatticeArgs &a, uint32_
     const uint32_t first_call = ((uint32_t)S * j) >> 1, par = ((uint32_t)S * j) & 1u;
     const bool lane0 = j == 0u, lanel = j == (uint32_t)(LPC - 1);
     int until_flush = flush_every;
+    uint32_t nacc = 0u; // accepted moves since the last flush (the same in every lane)
     for (int s = 0; s < a.n_sweeps; ++s) {
         const uint32_t g = a.g0 + (uint32_t)s;
         for (int y = 0; y < L; ++y) {
@@ -963,6 +1001,7 @@ __device__ __forceinline__ int32_t potts_lp_sweeps(const LatticeArgs &a, uint32_
             uint32_t F[2] = {0u, 0u};
             lp_row<L, LPC, TLDS>(geo, acw, gv2, gv1, av1, offp[0], rowb, F, T, std::make_integer_sequence<int, L>{});
             // flips were shifted in from the low end, first site highest
+            nacc += (uint32_t)__builtin_popcount(F[0]) + (uint32_t)__builtin_popcount(F[1]);
             const uint32_t F0 = __builtin_bitreverse32(F[0]) >> (32 - (L < 32 ? L : 32));
             const uint32_t F1 = L > 32 ? __builtin_bitreverse32(F[1]) >> (32 - (L > 32 ? L - 32 : 32)) : 0u;
             // this lane's accepted proposals: bits S j .. S j + S - 1 of F
@@ -985,11 +1024,13 @@ __device__ __forceinline__ int32_t potts_lp_sweeps(const LatticeArgs &a, uint32_
         }
         if (--until_flush == 0 && s + 1 < a.n_sweeps) {
             until_flush = flush_every;
+            flush_accepts(a, counts, nacc);
             __syncthreads();
             flush_hist(lhist, hw, a.hist);
             __syncthreads();
         }
     }
+    flush_accepts(a, counts, nacc);
     return bin_of(rowb);
 }
 
@@ -1061,11 +1102,17 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
             tbase = (int32_t)(uint32_t)(uintptr_t)(lds_u32 *)smem;
         int32_t rowb = TLDS ? tbase + 32 * b : 36 * b;
         auto bin_of = [&](int32_t rb) { return TLDS ? (rb - tbase) >> 5 : rb / 36; };
+        uint32_t nacc = 0u;
         for (int s = 0; s < a.n_sweeps; ++s) {
             const uint32_t g = a.g0 + (uint32_t)s;
             for (int y = 0; y < L; ++y) {
+                uint32_t before[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    before[w] = cur[w];
                 potts_row<L, LPC, TLDS, W>(up, cur, dn, rowb, T, chain, g, y, j, a.k0, a.k1, q,
                                            std::make_integer_sequence<int, L>{});
+                nacc += changed_bytes<W>(before, cur); // an accepted proposal changes the colour
                 const int yn = (y + 3) % L;
                 if (leader) {
 #pragma unroll
@@ -1086,11 +1133,13 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
             }
             if (--until_flush == 0 && s + 1 < a.n_sweeps) {
                 until_flush = flush_every;
+                flush_accepts(a, counts, nacc);
                 __syncthreads();
                 flush_hist(lhist, hw, a.hist);
                 __syncthreads();
             }
         }
+        flush_accepts(a, counts, nacc);
         b = bin_of(rowb);
     } else {
         constexpr int W = Row1<L>::W;
@@ -1109,15 +1158,21 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
         // sweep's final configuration, counted row by row once a row and the
         // one above it are final (the bond between rows L - 1 and 0 last)
         const bool em = MODEL == kMuma && a.em != nullptr;
-        uint32_t nmis = 0u;
+        uint32_t nmis = 0u, nacc = 0u;
         for (int s = 0; s < a.n_sweeps; ++s) {
             const uint32_t g = a.g0 + (uint32_t)s;
             for (int y = 0; y < L; ++y) {
-                if constexpr (LPC >= 4)
-                    ising_lp_row<MODEL, L, LPC, TLDS>(up, cur, dn, rowb, T, chain, g, y, j, a.k0, a.k1);
-                else
+                if constexpr (LPC >= 4) {
+                    ising_lp_row<MODEL, L, LPC, TLDS>(up, cur, dn, rowb, T, chain, g, y, j, a.k0, a.k1, nacc);
+                } else {
+                    uint32_t before[W];
+#pragma unroll
+                    for (int w = 0; w < W; ++w)
+                        before[w] = cur[w];
                     ising_row<MODEL, L, LPC, TLDS>(up, cur, dn, rowb, T, chain, g, y, j, a.k0, a.k1,
                                                    std::make_integer_sequence<int, W>{});
+                    nacc += changed_bits<W>(before, cur);
+                }
                 if constexpr (MODEL == kMuma) {
                     if (em) {
                         nmis += row_mis<L>(cur) + (y > 0 ? pair_mis<L>(up, cur) : 0u);
@@ -1149,11 +1204,13 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
                 nmis = 0u;
             if (--until_flush == 0 && s + 1 < a.n_sweeps) {
                 until_flush = flush_every;
+                flush_accepts(a, counts, nacc);
                 __syncthreads();
                 flush_hist(lhist, hw, a.hist);
                 __syncthreads();
             }
         }
+        flush_accepts(a, counts, nacc);
         b = (((rowb - tbase) >> 2) - row_origin<MODEL>()) / NC;
     }
     if (leader)

@@ -30,6 +30,7 @@ struct LatticeArgs {
     // MUMA only, or null: joint histogram [(N + 1) * n_bins] of the energy
     // row e = (E + 2N) / 4 and the magnetisation bin after each recorded sweep
     unsigned long long *em;
+    unsigned long long *accepts; // accepted moves of the recorded sweeps, or null
 };
 
 struct LatticeInitArgs {
@@ -56,6 +57,7 @@ struct PolymerArgs {
     int32_t chain0;             // global index of chain 0 in the random-number counters
     float step;
     int32_t moves;              // 1: spherical rotations and double bridging after the shifts
+    unsigned long long *accepts; // accepted moves of the recorded sweeps, or null
 };
 
 // Potential constants, each evaluated on the host once in a fixed order.

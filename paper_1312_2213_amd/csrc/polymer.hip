@@ -207,6 +207,7 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
     const bool counts = a.record && c < a.n_chains && j == 0;
     const uint32_t B = (uint32_t)a.n_bins;
     const int up_l = (j + 1) & 63, dn_l = (j + 63) & 63;
+    uint64_t nacc = 0u; // accepted moves of the recorded sweeps (wave-uniform)
 
     for (int s_ = 0; s_ < a.n_sweeps; ++s_) {
         const uint32_t g = a.g0 + (uint32_t)s_;
@@ -317,6 +318,7 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
                 }
                 E = En;
                 b = bn;
+                nacc += a.record ? 1u : 0u;
             }
             prev_acc = acc;
         }
@@ -399,6 +401,7 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
                     }
                     E = En;
                     b = bn;
+                    nacc += a.record ? 1u : 0u;
                 }
             }
             // one double bridging: bonds (bi, bi+1), (bj, bj+1) -> (bi, bj), (bi+1, bj+1)
@@ -461,6 +464,7 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
                         }
                         E = En;
                         b = bn;
+                        nacc += a.record ? 1u : 0u;
                     }
                 }
             }
@@ -479,6 +483,8 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
     if (j == 0) {
         a.energy[c] = E;
         a.bins[c] = b;
+        if (counts && a.accepts && nacc)
+            atomicAdd(a.accepts, (unsigned long long)nacc);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < a.n_bins; i += blockDim.x) {

@@ -68,8 +68,8 @@ int muca_polymer_geometry(const muca_config *c, Geometry *g)
     g->off_values = off;
     g->off_table = off;
     off = align256(off + (size_t)g->n_bins * g->n_bins * 4);
-    g->off_hist = off;
-    off = align256(off + (size_t)g->n_bins * 8);
+    g->off_hist = off; // histogram, then the count of accepted moves
+    off = align256(off + (size_t)(g->n_bins + 1) * 8);
     g->ws_bytes = off;
     return MUCA_OK;
 }
@@ -160,7 +160,7 @@ int muca_polymer_init(muca_run *r, const float *h_pos)
     if (e == hipSuccess)
         e = hipMemcpy(r->d_bins, bins.data(), bins.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = launch_fill_u64(r->d_hist, g.n_bins, r->stream);
+        e = launch_fill_u64(r->d_hist, g.n_bins + 1, r->stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(r->stream);
     if (e != hipSuccess)
@@ -232,6 +232,7 @@ int muca_polymer_enqueue(muca_run *r, int64_t sweeps, bool record, hipStream_t s
         a.chain0 = r->cfg.chain0;
         a.step = r->cfg.step;
         a.moves = r->cfg.moves;
+        a.accepts = r->d_hist + g.n_bins;
         hipError_t e = launch_polymer_sweeps(a, k, s);
         if (e != hipSuccess) {
             r->poisoned = true;

@@ -149,8 +149,8 @@ int muca_geometry(const muca_config *c, Geometry *g)
     off = align256(off + (size_t)g->c_pad * 4u);
     g->off_table = off;
     off = align256(off + tab_lds);
-    g->off_hist = off;
-    off = align256(off + (size_t)g->n_bins * 8u);
+    g->off_hist = off; // histogram, then the count of accepted moves
+    off = align256(off + (size_t)(g->n_bins + 1) * 8u);
     g->ws_bytes = off;
     return MUCA_OK;
 }
@@ -500,7 +500,7 @@ extern "C" int muca_init(const muca_config *c, void *d_ws, uint64_t ws_bytes, co
     a.chain0 = c->chain0;
     hipError_t e = launch_lattice_init(a, r->stream);
     if (e == hipSuccess)
-        e = launch_fill_u64(r->d_hist, g.n_bins, r->stream);
+        e = launch_fill_u64(r->d_hist, g.n_bins + 1, r->stream);
     std::vector<int32_t> bins(g.c_pad);
     if (e == hipSuccess)
         e = hipMemcpyAsync(bins.data(), r->d_bins, bins.size() * 4u, hipMemcpyDeviceToHost, r->stream);
@@ -554,6 +554,7 @@ int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s,
         a.table_in_lds = g.table_in_lds ? 1 : 0;
         a.chain0 = r->cfg.chain0;
         a.em = em;
+        a.accepts = r->d_hist + g.n_bins;
         HIP_OR_POISON(r, launch_lattice_sweeps(g.model, g.L, g.layout, g.lpc, g.cpb, a, s));
         r->sweep += (uint32_t)n;
         done += n;
@@ -620,7 +621,7 @@ extern "C" int muca_thermalize(muca_run *r, int64_t sweeps, void *stream)
     return sweeps ? muca_enqueue_sweeps(r, sweeps, false, r->stream) : MUCA_OK;
 }
 
-int muca_finish_iteration(muca_run *r, const uint64_t *H, muca_iter_stats *st)
+int muca_finish_iteration(muca_run *r, const uint64_t *H, uint64_t accepted, muca_iter_stats *st)
 {
     const Geometry &g = r->g;
     const int B = g.n_bins;
@@ -629,6 +630,10 @@ int muca_finish_iteration(muca_run *r, const uint64_t *H, muca_iter_stats *st)
     muca_iter_stats s{};
     s.iteration = r->iteration;
     s.sweeps = r->pending;
+    // attempts per chain and sweep: every site (bead); the polymer's full
+    // move set adds a rotation per bead and one double bridging
+    const double per_sweep = g.model == kPolymer && r->cfg.moves ? 2.0 * g.n_sites + 1.0 : (double)g.n_sites;
+    s.accept_rate = (double)accepted / ((double)r->pending * (double)r->cfg.n_chains * per_sweep);
     s.lo_visited = -1;
     s.hi_visited = -1;
     for (int b = 0; b < B; ++b) {
@@ -667,11 +672,11 @@ extern "C" int muca_merge_update(muca_run *r, muca_iter_stats *st)
     if (r->pending <= 0)
         return muca_fail(MUCA_E_STATE, "merge_update without sweeps since the last merge");
     const int B = r->g.n_bins;
-    std::vector<uint64_t> H(B);
+    std::vector<uint64_t> H(B + 1); // the histogram and the accepted-move count behind it
     HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
-    HIP_OR_POISON(r, hipMemcpy(H.data(), r->d_hist, (size_t)B * 8u, hipMemcpyDeviceToHost));
-    HIP_OR_POISON(r, launch_fill_u64(r->d_hist, B, r->stream));
-    return muca_finish_iteration(r, H.data(), st);
+    HIP_OR_POISON(r, hipMemcpy(H.data(), r->d_hist, (size_t)(B + 1) * 8u, hipMemcpyDeviceToHost));
+    HIP_OR_POISON(r, launch_fill_u64(r->d_hist, B + 1, r->stream));
+    return muca_finish_iteration(r, H.data(), H[B], st);
 }
 
 extern "C" int muca_get_pending_hist(const muca_run *r_, uint64_t *h, int64_t n)
@@ -698,9 +703,11 @@ extern "C" int muca_merge_update_hist(muca_run *r, const uint64_t *h, int64_t n,
         return muca_fail(MUCA_E_ARG, "need a merged histogram of n_bins = %d entries", r->g.n_bins);
     if (r->pending <= 0)
         return muca_fail(MUCA_E_STATE, "merge_update without sweeps since the last merge");
+    uint64_t accepted = 0;
     HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
-    HIP_OR_POISON(r, launch_fill_u64(r->d_hist, r->g.n_bins, r->stream));
-    return muca_finish_iteration(r, h, st);
+    HIP_OR_POISON(r, hipMemcpy(&accepted, r->d_hist + r->g.n_bins, 8u, hipMemcpyDeviceToHost));
+    HIP_OR_POISON(r, launch_fill_u64(r->d_hist, r->g.n_bins + 1, r->stream));
+    return muca_finish_iteration(r, h, accepted, st);
 }
 
 extern "C" int muca_reweight(const muca_run *r, const double *betas, int32_t n, double *out)

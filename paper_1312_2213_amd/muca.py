@@ -47,7 +47,7 @@ class muca_config(ctypes.Structure):
 class muca_iter_stats(ctypes.Structure):
     _fields_ = [("iteration", ctypes.c_int64), ("sweeps", ctypes.c_int64), ("samples", ctypes.c_int64),
                 ("flatness", ctypes.c_double), ("flat", ctypes.c_int32), ("lo_visited", ctypes.c_int32),
-                ("hi_visited", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("hi_visited", ctypes.c_int32), ("reserved", ctypes.c_int32), ("accept_rate", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
