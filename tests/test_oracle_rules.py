@@ -222,3 +222,26 @@ def test_potts_colours_stay_below_q_for_large_q(orc):
         s = o.spins[c].reshape(8, 8).astype(int)
         E += int(np.sum(s != np.roll(s, -1, 1)) + np.sum(s != np.roll(s, -1, 0)))
         assert E == o.E[c]
+
+
+# ------------------------------------------------------- accepted-move count
+def test_accepted_move_count(orc):
+    """lnW = 0 over the full range accepts every lattice move; zero
+    thresholds accept none; thermalisation sweeps are not counted; a
+    polymer shift that is accepted moves its bead, so one sweep's count is
+    the number of beads that moved."""
+    from synth import polymer_walk
+    for model, q in ((orc.ISING, 2), (orc.POTTS, 5), (orc.MUMA, 2)):
+        r = orc.LatticeRun(model, 8, 3, 2, q=q, beta=0.0)
+        r.sweeps(4)
+        assert r.take_accepted() == 4 * 3 * 64
+        r.sweeps(4, record=False)
+        assert r.take_accepted() == 0
+        r.sweeps(2, T=np.zeros(r.n_bins * r.n_cols, np.uint32))
+        assert r.take_accepted() == 0
+    pos = polymer_walk(12, 4, 1)
+    p = orc.PolymerRun(n_beads=12, n_chains=4, seed=1, pos=pos)
+    before = p.pos.copy()
+    p.sweeps(1)
+    moved = int(np.any(p.pos != before, axis=2).sum())
+    assert p.take_accepted() == moved and moved > 0
