@@ -197,6 +197,30 @@ int muca_reweight(const muca_run *run, const double *betas, int32_t n, double *o
  *     weights of the last merged iteration (the lnW^(n) of muca_reweight).
  *     MUCA_E_STATE before the first merge, MUCA_E_ARG for a size mismatch,
  *     null pointers or n < 1. */
+/* Per-block histograms and jackknife errors of the reweighted observables
+ * (Eq. 2 over the merged histogram; the blocks are independent groups of
+ * chains, so leaving one out at a time gives the statistical error of any
+ * reweighted average).  Lattice runs.
+ *   muca_blocks_shape: n_blocks = the number of chain blocks (workgroups of
+ *     the run's plain launch) and chains_per_block; block k holds chains
+ *     [k * chains_per_block, (k + 1) * chains_per_block), padding chains
+ *     (>= n_chains) never counted.  MUCA_E_ARG for a polymer run.
+ *   muca_run_iteration_blocks: muca_run_iteration that also adds each
+ *     block's histogram to d_blocks[k * n_bins + b] (device memory, n_blocks
+ *     * n_bins uint64, owned by the caller, accumulated into, never
+ *     cleared).  The chains and H are those of muca_run_iteration.
+ *   muca_reweight_jackknife: from the host copy h_blocks of block
+ *     histograms recorded with the weights of the last merged iteration,
+ *     out[4q..4q+3] = muca_reweight's values over their sum and
+ *     err[4q..4q+3] = their jackknife errors sqrt((m-1)/m sum_k (v_k -
+ *     mean)^2) over the m non-empty blocks, v_k the values without block k.
+ *     MUCA_E_STATE before the first merge; MUCA_E_ARG for null pointers,
+ *     n < 1 or fewer than two non-empty blocks. */
+int muca_blocks_shape(const muca_run *run, int32_t *n_blocks, int32_t *chains_per_block);
+int muca_run_iteration_blocks(muca_run *run, int64_t sweeps, uint64_t *d_blocks, void *stream);
+int muca_reweight_jackknife(const muca_run *run, const uint64_t *h_blocks, int32_t n_blocks, const double *betas,
+                            int32_t n, double *out, double *err);
+
 int muca_em_shape(const muca_run *run, int32_t *n_e, int32_t *n_m);
 int muca_run_iteration_em(muca_run *run, int64_t sweeps, uint64_t *d_em, void *stream);
 int muca_reweight_em(const muca_run *run, const uint64_t *h_em, int64_t n_em, const double *betas, int32_t n,

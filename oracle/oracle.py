@@ -350,6 +350,26 @@ def reweight(H, lnW, values, nsite, beta, muma=False):
     return o
 
 
+def reweight_jackknife(H_blocks, lnW, values, nsite, betas, muma=False):
+    """Reweighted averages (Eq. 2, as reweight()) over the sum of the block
+    histograms, and their jackknife errors: with v_k the values when block k
+    is left out, over the m blocks that hold any count,
+    err = sqrt((m - 1) / m * sum_k (v_k - mean_k v_k)^2).  Returns (values,
+    errors), each len(betas) x 4."""
+    Hb = np.asarray(H_blocks, np.uint64)
+    used = [k for k in range(Hb.shape[0]) if Hb[k].sum() > 0]
+    H = Hb.sum(axis=0, dtype=np.uint64)
+    m = len(used)
+    vals = np.zeros((len(betas), 4))
+    errs = np.zeros((len(betas), 4))
+    for q, beta in enumerate(betas):
+        vals[q] = reweight(H, lnW, values, nsite, beta, muma)
+        v = np.array([reweight(H - Hb[k], lnW, values, nsite, beta, muma) for k in used])
+        mean = v.sum(axis=0) / m
+        errs[q] = np.sqrt((m - 1.0) / m * ((v - mean) ** 2).sum(axis=0))
+    return vals, errs
+
+
 def reweight_em(HEM, lnW, L, lo, beta, betas) -> np.ndarray:
     """orc_reweight_em over the rows E = -2N + 4e and the columns
     M = lo + 2b of a multimagnetic run at inverse temperature beta."""

@@ -648,7 +648,8 @@ __device__ __forceinline__ void potts_row(const uint32_t (&up)[W], uint32_t (&cu
 
 // Adds the block's packed LDS counters to the global histogram and clears
 // them.  Called by every thread of the block between two barriers.
-__device__ __forceinline__ void flush_hist(uint32_t *lhist, int hw, unsigned long long *hist)
+__device__ __forceinline__ void flush_hist(uint32_t *lhist, int hw, unsigned long long *hist,
+                                           unsigned long long *blk = nullptr)
 {
     for (int i = threadIdx.x; i < hw; i += blockDim.x) {
         const uint32_t v = lhist[i];
@@ -658,6 +659,12 @@ __device__ __forceinline__ void flush_hist(uint32_t *lhist, int hw, unsigned lon
                 atomicAdd(&hist[2 * i], (unsigned long long)(v & 0xFFFFu));
             if (v >> 16)
                 atomicAdd(&hist[2 * i + 1], (unsigned long long)(v >> 16));
+            if (blk) { // this block's own histogram, for jackknife errors
+                if (v & 0xFFFFu)
+                    atomicAdd(&blk[2 * i], (unsigned long long)(v & 0xFFFFu));
+                if (v >> 16)
+                    atomicAdd(&blk[2 * i + 1], (unsigned long long)(v >> 16));
+            }
         }
     }
 }
@@ -895,7 +902,7 @@ template <int L, int LPC, bool TLDS>
 __device__ __forceinline__ int32_t potts_lp_sweeps(const LatticeArgs &a, uint32_t *base, size_t stride,
                                                    uint32_t chain, uint32_t j, bool counts, int32_t b,
                                                    const uint32_t *__restrict__ T, int32_t tbase, uint32_t *lhist,
-                                                   int hw, int flush_every)
+                                                   int hw, int flush_every, unsigned long long *blk)
 {
     using P = PottsLP<L, LPC>;
     constexpr int S = P::S, SW = P::SW, NCALL = P::NCALL, KC = L / 2; // Philox calls per row
@@ -1026,7 +1033,7 @@ __device__ __forceinline__ int32_t potts_lp_sweeps(const LatticeArgs &a, uint32_
             until_flush = flush_every;
             flush_accepts(a, counts, nacc);
             __syncthreads();
-            flush_hist(lhist, hw, a.hist);
+            flush_hist(lhist, hw, a.hist, blk);
             __syncthreads();
         }
     }
@@ -1078,12 +1085,16 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
     // sweeps between two flushes of the 16-bit LDS counters
     const int flush_every = kMaxBlockCount / (int)(blockDim.x / LPC);
     int until_flush = flush_every;
+    // this block's histogram (plain launches with per-block histograms)
+    unsigned long long *blk =
+        a.hist_blocks ? a.hist_blocks + (size_t)(c_first / (int)(blockDim.x / LPC)) * (size_t)a.n_bins : nullptr;
 
     if constexpr (MODEL == kPotts && PottsLP<L, LPC>::ok) {
         int32_t tbase = 0;
         if constexpr (TLDS)
             tbase = (int32_t)(uint32_t)(uintptr_t)(lds_u32 *)smem;
-        b = potts_lp_sweeps<L, LPC, TLDS>(a, base, stride, chain, j, counts, b, T, tbase, lhist, hw, flush_every);
+        b = potts_lp_sweeps<L, LPC, TLDS>(a, base, stride, chain, j, counts, b, T, tbase, lhist, hw, flush_every,
+                                          blk);
     } else if constexpr (MODEL == kPotts) {
         constexpr int W = Geom<L, LAYOUT>::kWpr;
         const uint32_t q = (uint32_t)a.q;
@@ -1135,7 +1146,7 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
                 until_flush = flush_every;
                 flush_accepts(a, counts, nacc);
                 __syncthreads();
-                flush_hist(lhist, hw, a.hist);
+                flush_hist(lhist, hw, a.hist, blk);
                 __syncthreads();
             }
         }
@@ -1206,7 +1217,7 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
                 until_flush = flush_every;
                 flush_accepts(a, counts, nacc);
                 __syncthreads();
-                flush_hist(lhist, hw, a.hist);
+                flush_hist(lhist, hw, a.hist, blk);
                 __syncthreads();
             }
         }
@@ -1216,7 +1227,7 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
     if (leader)
         a.bins[c] = b;
     __syncthreads();
-    flush_hist(lhist, hw, a.hist);
+    flush_hist(lhist, hw, a.hist, blk);
 }
 
 template <int MODEL, int L, int LAYOUT, bool TLDS, int LPC>

@@ -31,6 +31,9 @@ struct LatticeArgs {
     // row e = (E + 2N) / 4 and the magnetisation bin after each recorded sweep
     unsigned long long *em;
     unsigned long long *accepts; // accepted moves of the recorded sweeps, or null
+    // or null: one histogram [n_bins] per block of chains (the plain launch's
+    // workgroups, chains [k * cpb, (k + 1) * cpb)), for jackknife errors
+    unsigned long long *hist_blocks;
 };
 
 struct LatticeInitArgs {

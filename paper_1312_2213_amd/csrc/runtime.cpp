@@ -526,7 +526,8 @@ extern "C" int muca_init(const muca_config *c, void *d_ws, uint64_t ws_bytes, co
     return MUCA_OK;
 }
 
-int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s, unsigned long long *em)
+int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s, unsigned long long *em,
+                        unsigned long long *hist_blocks)
 {
     if (r->g.model == kPolymer)
         return muca_polymer_enqueue(r, sweeps, record, s);
@@ -555,6 +556,7 @@ int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s,
         a.chain0 = r->cfg.chain0;
         a.em = em;
         a.accepts = r->d_hist + g.n_bins;
+        a.hist_blocks = hist_blocks;
         HIP_OR_POISON(r, launch_lattice_sweeps(g.model, g.L, g.layout, g.lpc, g.cpb, a, s));
         r->sweep += (uint32_t)n;
         done += n;
@@ -604,6 +606,40 @@ extern "C" int muca_run_iteration_em(muca_run *r, int64_t sweeps, uint64_t *d_em
         return muca_fail(MUCA_E_ARG, "sweeps must be >= 1");
     r->stream = (hipStream_t)stream;
     rc = muca_enqueue_sweeps(r, sweeps, true, r->stream, (unsigned long long *)d_em);
+    if (rc)
+        return rc;
+    r->pending += sweeps;
+    return MUCA_OK;
+}
+
+extern "C" int muca_blocks_shape(const muca_run *r, int32_t *n_blocks, int32_t *chains_per_block)
+{
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    const Geometry &g = r->g;
+    if (g.model == kPolymer)
+        return muca_fail(MUCA_E_ARG, "per-block histograms: lattice runs only");
+    if (n_blocks)
+        *n_blocks = (int32_t)(((int64_t)g.c_pad * g.lpc) / g.cpb);
+    if (chains_per_block)
+        *chains_per_block = g.cpb / g.lpc;
+    return MUCA_OK;
+}
+
+extern "C" int muca_run_iteration_blocks(muca_run *r, int64_t sweeps, uint64_t *d_blocks, void *stream)
+{
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (r->g.model == kPolymer)
+        return muca_fail(MUCA_E_ARG, "per-block histograms: lattice runs only");
+    if (!d_blocks)
+        return muca_fail(MUCA_E_ARG, "null block histograms");
+    if (sweeps < 1)
+        return muca_fail(MUCA_E_ARG, "sweeps must be >= 1");
+    r->stream = (hipStream_t)stream;
+    rc = muca_enqueue_sweeps(r, sweeps, true, r->stream, nullptr, (unsigned long long *)d_blocks);
     if (rc)
         return rc;
     r->pending += sweeps;
@@ -813,6 +849,79 @@ extern "C" int muca_reweight_em(const muca_run *r, const uint64_t *h_em, int64_t
     for (int k = 0; k < n; ++k)
         reweight_joint(NE, B, h_em, r->lnW_last.data(), r->cfg.lo, g.step, g.n_sites, r->cfg.beta, betas[k],
                        out + 6 * k);
+    return MUCA_OK;
+}
+
+// Values of the binned quantity per bin (energy; MUMA: magnetisation; Potts
+// E_unsat - 2N; polymer bin centres), as muca_reweight reports them.
+static std::vector<double> bin_values(const muca_run *r)
+{
+    const Geometry &g = r->g;
+    std::vector<double> val(g.n_bins);
+    for (int b = 0; b < g.n_bins; ++b) {
+        if (g.model == kIsing || g.model == kMuma)
+            val[b] = (double)(r->cfg.lo + g.step * b);
+        else if (g.model == kPotts)
+            val[b] = (double)(r->cfg.lo + b) - 2.0 * g.n_sites;
+        else
+            val[b] = r->cfg.x_lo + ((r->cfg.x_hi - r->cfg.x_lo) / (double)g.n_bins) * ((double)b + 0.5);
+    }
+    return val;
+}
+
+extern "C" int muca_reweight_jackknife(const muca_run *r, const uint64_t *h_blocks, int32_t n_blocks,
+                                       const double *betas, int32_t n, double *out, double *err)
+{
+    int rc = check_run(r);
+    if (rc)
+        return rc;
+    if (!r->have_last)
+        return muca_fail(MUCA_E_STATE, "no merged histogram yet");
+    const Geometry &g = r->g;
+    const bool muma = g.model == kMuma;
+    if (!h_blocks || n_blocks < 1 || n < 1 || !out || !err || (!muma && !betas))
+        return muca_fail(MUCA_E_ARG, "need block histograms, n >= 1, betas and output arrays");
+    const int B = g.n_bins;
+    // the blocks that saw any chain, and their sum
+    std::vector<int> used;
+    std::vector<uint64_t> H(B, 0), Hk(B);
+    for (int k = 0; k < n_blocks; ++k) {
+        uint64_t tot = 0;
+        for (int b = 0; b < B; ++b) {
+            H[b] += h_blocks[(size_t)k * B + b];
+            tot += h_blocks[(size_t)k * B + b];
+        }
+        if (tot)
+            used.push_back(k);
+    }
+    if (used.size() < 2)
+        return muca_fail(MUCA_E_ARG, "jackknife needs at least two non-empty blocks");
+    const std::vector<double> val = bin_values(r);
+    const double m = (double)used.size();
+    std::vector<double> v(4 * used.size());
+    for (int q = 0; q < n; ++q) {
+        const double beta = muma ? r->cfg.beta : betas[q];
+        muca_reweight_bins(B, H.data(), r->lnW_last.data(), val.data(), g.n_sites, muma, beta, out + 4 * q);
+        for (size_t u = 0; u < used.size(); ++u) { // leave block used[u] out
+            const uint64_t *hk = h_blocks + (size_t)used[u] * B;
+            for (int b = 0; b < B; ++b)
+                Hk[b] = H[b] - hk[b];
+            muca_reweight_bins(B, Hk.data(), r->lnW_last.data(), val.data(), g.n_sites, muma, beta,
+                               v.data() + 4 * u);
+        }
+        for (int c = 0; c < 4; ++c) {
+            double mean = 0.0;
+            for (size_t u = 0; u < used.size(); ++u)
+                mean += v[4 * u + c];
+            mean /= m;
+            double ss = 0.0;
+            for (size_t u = 0; u < used.size(); ++u) {
+                const double d = v[4 * u + c] - mean;
+                ss += d * d;
+            }
+            err[4 * q + c] = std::sqrt((m - 1.0) / m * ss);
+        }
+    }
     return MUCA_OK;
 }
 

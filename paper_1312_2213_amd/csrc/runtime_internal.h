@@ -53,7 +53,7 @@ int muca_fail(int code, const char *fmt, ...);
 int muca_geometry(const muca_config *c, muca::Geometry *g);
 int muca_rebuild_thresholds(muca_run *r);
 int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s,
-                        unsigned long long *em = nullptr);
+                        unsigned long long *em = nullptr, unsigned long long *hist_blocks = nullptr);
 int muca_finish_iteration(muca_run *r, const uint64_t *H, uint64_t accepted, muca_iter_stats *st);
 uint32_t muca_threshold_of(double D);
 void muca_recursion(int B, const uint8_t *m, const uint64_t *H, double *lnR, double *P, double *lnW);

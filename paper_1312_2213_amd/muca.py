@@ -70,6 +70,9 @@ def _load():
         "muca_get_pending_hist": (ctypes.c_int, [vp, vp, i64]),
         "muca_merge_update_hist": (ctypes.c_int, [vp, vp, i64, P(muca_iter_stats)]),
         "muca_reweight": (ctypes.c_int, [vp, vp, i32, vp]),
+        "muca_blocks_shape": (ctypes.c_int, [vp, P(i32), P(i32)]),
+        "muca_run_iteration_blocks": (ctypes.c_int, [vp, i64, vp, vp]),
+        "muca_reweight_jackknife": (ctypes.c_int, [vp, vp, i32, vp, i32, vp, vp]),
         "muca_em_shape": (ctypes.c_int, [vp, P(i32), P(i32)]),
         "muca_run_iteration_em": (ctypes.c_int, [vp, i64, vp, vp]),
         "muca_reweight_em": (ctypes.c_int, [vp, vp, i64, vp, i32, vp]),
@@ -100,7 +103,8 @@ def _load():
 LIB = _load()
 EXPORTED = ("muca_config_default", "muca_workspace_bytes", "muca_init", "muca_run_iteration",
             "muca_thermalize", "muca_merge_update", "muca_get_pending_hist", "muca_merge_update_hist",
-            "muca_reweight", "muca_em_shape", "muca_run_iteration_em", "muca_reweight_em",
+            "muca_reweight", "muca_blocks_shape", "muca_run_iteration_blocks", "muca_reweight_jackknife",
+            "muca_em_shape", "muca_run_iteration_em", "muca_reweight_em",
             "muca_batch_workspace_bytes",
             "muca_batch_create", "muca_batch_run_iteration", "muca_batch_free", "muca_autotune", "muca_sizes", "muca_get_lnw", "muca_get_last_hist",
             "muca_get_thresholds", "muca_get_chain_state", "muca_set_lnw", "muca_set_thresholds",
@@ -166,6 +170,35 @@ class Run:
     # -- the hot path ------------------------------------------------------
     def run_iteration(self, sweeps: int, stream=None):
         _check(LIB.muca_run_iteration(self.handle, int(sweeps), _stream_handle(stream or self.stream)))
+
+    def blocks_shape(self) -> tuple[int, int]:
+        """(n_blocks, chains_per_block) of the per-block histograms."""
+        nb, cpb = ctypes.c_int32(), ctypes.c_int32()
+        _check(LIB.muca_blocks_shape(self.handle, ctypes.byref(nb), ctypes.byref(cpb)))
+        return nb.value, cpb.value
+
+    def run_iteration_blocks(self, sweeps: int, blocks, stream=None):
+        """run_iteration that also adds each chain block's histogram to
+        `blocks`, a contiguous 64-bit integer device tensor of n_blocks *
+        n_bins entries (accumulated into, never cleared)."""
+        import torch
+        nb, _ = self.blocks_shape()
+        if not (isinstance(blocks, torch.Tensor) and blocks.is_cuda and blocks.dtype in (torch.uint64, torch.int64)
+                and blocks.is_contiguous() and blocks.numel() == nb * self.n_bins):
+            raise ValueError(f"blocks must be a contiguous 64-bit integer CUDA tensor of {nb} x {self.n_bins}")
+        _check(LIB.muca_run_iteration_blocks(self.handle, int(sweeps), ctypes.c_void_p(blocks.data_ptr()),
+                                             _stream_handle(stream or self.stream)))
+
+    def reweight_jackknife(self, h_blocks, betas=None):
+        """(values, jackknife errors), each n x 4 as reweight(), from host
+        block histograms recorded with the last merged iteration's weights."""
+        h = np.ascontiguousarray(h_blocks, np.uint64)
+        nb = h.size // self.n_bins
+        b = np.ascontiguousarray(np.atleast_1d(betas if betas is not None else [0.0]), np.float64)
+        out = np.zeros((len(b), 4), np.float64)
+        err = np.zeros((len(b), 4), np.float64)
+        _check(LIB.muca_reweight_jackknife(self.handle, _ptr(h), nb, _ptr(b), len(b), _ptr(out), _ptr(err)))
+        return out, err
 
     def em_shape(self) -> tuple[int, int]:
         """(n_e, n_m) of the joint (E, M) histogram of a multimagnetic run."""

@@ -245,3 +245,25 @@ def test_accepted_move_count(orc):
     p.sweeps(1)
     moved = int(np.any(p.pos != before, axis=2).sum())
     assert p.take_accepted() == moved and moved > 0
+
+
+# ------------------------------------------------------------- jackknife
+def test_jackknife_of_a_mean_is_the_standard_error(orc):
+    """At lnW = 0 and beta = 0 the reweighted <E> is the histogram mean; with
+    equal counts per block the jackknife error of a mean is the standard
+    error of the block means, sqrt(sum (mu_k - mu)^2 / (m (m - 1))); equal
+    blocks give zero; empty blocks are left out."""
+    rng = np.random.default_rng(5)
+    B, m, c = 17, 9, 400
+    values = np.arange(B, dtype=np.float64) * 4.0 - 32.0
+    blocks = np.zeros((m + 2, B), np.uint64)
+    for k in range(m):
+        blocks[k] = rng.multinomial(c, rng.dirichlet(np.ones(B)))
+    vals, errs = orc.reweight_jackknife(blocks, np.zeros(B), values, 64, [0.0])
+    mu = (blocks[:m] * values).sum(axis=1) / c
+    want = math.sqrt(((mu - mu.mean()) ** 2).sum() / (m * (m - 1)))
+    assert vals[0][2] == pytest.approx(mu.mean(), rel=1e-13)
+    assert errs[0][2] == pytest.approx(want, rel=1e-10)
+    same = np.tile(blocks[0], (5, 1))
+    _, e0 = orc.reweight_jackknife(same, np.zeros(B), values, 64, [0.3, 0.7])
+    assert np.all(np.abs(e0) < 1e-12)
