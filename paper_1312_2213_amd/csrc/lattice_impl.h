@@ -376,11 +376,9 @@ __device__ __forceinline__ void ilp_site(const uint64_t (&pk)[RowRng<L, LPC, 1>:
     B = prev ? Bf : B;   // this site's bin row
     Bf = prev ? x1 : x0; // the next site's, if this one flips
     uint32_t n_t0 = 0u, n_t1 = 0u;
-    uint64_t nxt = 0u;
     if constexpr (X + 1 < L) {
         n_t0 = load_t<TLDS>(T, B + sbyte(D));
         n_t1 = load_t<TLDS>(T, Bf + sbyte(D >> 8));
-        nxt = ilp_get<L, LPC, X + 1>(pk, dv2, dv1, f0);
     }
     // selected only now, after the next reads were issued (the barrier keeps
     // the wait for this site's reads one site behind them)
@@ -388,7 +386,10 @@ __device__ __forceinline__ void ilp_site(const uint64_t (&pk)[RowRng<L, LPC, 1>:
     const uint32_t t = prev ? t1 : t0;
     t0 = n_t0;
     t1 = n_t1;
-    cur = nxt;
+    // the next site's descriptor, broadcast beside the compare (this site's
+    // descriptor is dead by now, and the reads above are a few instructions back)
+    if constexpr (X + 1 < L)
+        cur = ilp_get<L, LPC, X + 1>(pk, dv2, dv1, f0);
     if constexpr (X > 0)
         F[(X - 1) / 32] = shift_in<false>(F[(X - 1) / 32], pm);
     const bool acc = r < t;
