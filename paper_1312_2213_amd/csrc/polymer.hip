@@ -177,8 +177,9 @@ __device__ __forceinline__ void quat_rotate(double w, double x, double y, double
 
 // One chain per wavefront.  Lane j holds bead j and, with TWO (64 < N <= 128),
 // bead j + 64 (register set 1).  A pair sum slot is lane j's term plus, with
-// TWO, the term of bead j + 64.
-template <bool TWO>
+// TWO, the term of bead j + 64.  MOVES: the paper's full move set (a
+// separate variant, so the shift-only kernel carries none of its registers).
+template <bool TWO, bool MOVES>
 __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams p)
 {
     extern __shared__ uint32_t lhist[];
@@ -322,7 +323,7 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
             }
             prev_acc = acc;
         }
-        if (a.moves) {
+        if constexpr (MOVES) {
             // position of bead k, the same in every lane
             auto bead = [&](int k, float &px, float &py, float &pz) {
                 const int l = k & 63;
@@ -511,10 +512,18 @@ hipError_t launch_polymer_sweeps(const PolymerArgs &a, const PolymerConsts &k, h
     if (chains_per_block < 1 || chains_per_block > 4 || a.c_pad % chains_per_block)
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)(a.c_pad / chains_per_block)), block((unsigned)(64 * chains_per_block));
-    if (a.n_beads > 64)
-        hipLaunchKernelGGL(polymer_sweeps<true>, grid, block, (size_t)a.n_bins * 4u, s, a, p);
-    else
-        hipLaunchKernelGGL(polymer_sweeps<false>, grid, block, (size_t)a.n_bins * 4u, s, a, p);
+    const size_t lds = (size_t)a.n_bins * 4u;
+    if (a.n_beads > 64) {
+        if (a.moves)
+            hipLaunchKernelGGL((polymer_sweeps<true, true>), grid, block, lds, s, a, p);
+        else
+            hipLaunchKernelGGL((polymer_sweeps<true, false>), grid, block, lds, s, a, p);
+    } else {
+        if (a.moves)
+            hipLaunchKernelGGL((polymer_sweeps<false, true>), grid, block, lds, s, a, p);
+        else
+            hipLaunchKernelGGL((polymer_sweeps<false, false>), grid, block, lds, s, a, p);
+    }
     return hipGetLastError();
 }
 
