@@ -292,6 +292,8 @@ extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, in
         muca_run *r = runs[i];
         if (!r || r->poisoned)
             return muca_fail(MUCA_E_STATE, "run %d is null or poisoned", i);
+        if (int rc = muca_use_stream(r, s))
+            return rc; // the run's last threshold upload may still be queued elsewhere
         const int kind = kind_of(r), li = l_index(r->g.L);
         if (kind < 0 || li < 0)
             return muca_fail(MUCA_E_ARG, "run %d (model %d, L %d) has no batched variant", i, r->g.model, r->g.L);
@@ -375,7 +377,6 @@ extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, in
     for (int i = 0; i < n; ++i) {
         runs[i]->sweep += (uint32_t)sweeps[i];
         runs[i]->pending += sweeps[i];
-        runs[i]->stream = s;
     }
     return MUCA_OK;
 }

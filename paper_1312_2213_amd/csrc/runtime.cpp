@@ -409,13 +409,24 @@ static int check_run(const muca_run *r)
     return MUCA_OK;
 }
 
+muca_run::~muca_run()
+{
+    if (h_hist)
+        (void)hipHostFree(h_hist);
+    if (h_table)
+        (void)hipHostFree(h_table);
+}
+
+// The table goes out through the pinned staging buffer without a wait: the
+// next launch on the run's stream is ordered after the copy, a switch to
+// another stream waits for it, and every caller synchronised the stream
+// before, so no earlier copy still reads the staging buffer.
 static int upload_thresholds(muca_run *r)
 {
     if (r->g.model == kPolymer)
         return muca_polymer_upload(r);
-    HIP_OR_POISON(r, hipMemcpyAsync(r->d_table, r->T.data(), r->T.size() * 4u, hipMemcpyHostToDevice,
-                                    r->stream));
-    HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
+    std::memcpy(r->h_table, r->T.data(), r->T.size() * 4u);
+    HIP_OR_POISON(r, hipMemcpyAsync(r->d_table, r->h_table, r->T.size() * 4u, hipMemcpyHostToDevice, r->stream));
     return MUCA_OK;
 }
 
@@ -473,6 +484,15 @@ extern "C" int muca_init(const muca_config *c, void *d_ws, uint64_t ws_bytes, co
     r->P.assign(g.n_bins, 0.0);
     r->H_last.assign(g.n_bins, 0u);
     r->lnW_last.assign(g.n_bins, 0.0);
+    if (g.model != kPolymer) {
+        hipError_t e = hipHostMalloc((void **)&r->h_hist, (size_t)(g.n_bins + 1) * 8u, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&r->h_table, (size_t)g.n_bins * g.n_cols * 4u, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            delete r;
+            return muca_fail(MUCA_E_HIP, "init: pinned staging: %s", hipGetErrorString(e));
+        }
+    }
     if (g.model == kPolymer) {
         rc = muca_polymer_init(r, h_pos);
         if (rc) {
@@ -564,6 +584,14 @@ int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s,
     return MUCA_OK;
 }
 
+int muca_use_stream(muca_run *r, hipStream_t s)
+{
+    if (r->stream != s)
+        HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
+    r->stream = s;
+    return MUCA_OK;
+}
+
 extern "C" int muca_run_iteration(muca_run *r, int64_t sweeps, void *stream)
 {
     int rc = check_run(r);
@@ -571,7 +599,9 @@ extern "C" int muca_run_iteration(muca_run *r, int64_t sweeps, void *stream)
         return rc;
     if (sweeps < 1)
         return muca_fail(MUCA_E_ARG, "sweeps must be >= 1");
-    r->stream = (hipStream_t)stream;
+    rc = muca_use_stream(r, (hipStream_t)stream);
+    if (rc)
+        return rc;
     rc = muca_enqueue_sweeps(r, sweeps, true, r->stream);
     if (rc)
         return rc;
@@ -604,7 +634,9 @@ extern "C" int muca_run_iteration_em(muca_run *r, int64_t sweeps, uint64_t *d_em
         return muca_fail(MUCA_E_ARG, "null joint histogram");
     if (sweeps < 1)
         return muca_fail(MUCA_E_ARG, "sweeps must be >= 1");
-    r->stream = (hipStream_t)stream;
+    rc = muca_use_stream(r, (hipStream_t)stream);
+    if (rc)
+        return rc;
     rc = muca_enqueue_sweeps(r, sweeps, true, r->stream, (unsigned long long *)d_em);
     if (rc)
         return rc;
@@ -638,7 +670,9 @@ extern "C" int muca_run_iteration_blocks(muca_run *r, int64_t sweeps, uint64_t *
         return muca_fail(MUCA_E_ARG, "null block histograms");
     if (sweeps < 1)
         return muca_fail(MUCA_E_ARG, "sweeps must be >= 1");
-    r->stream = (hipStream_t)stream;
+    rc = muca_use_stream(r, (hipStream_t)stream);
+    if (rc)
+        return rc;
     rc = muca_enqueue_sweeps(r, sweeps, true, r->stream, nullptr, (unsigned long long *)d_blocks);
     if (rc)
         return rc;
@@ -653,7 +687,9 @@ extern "C" int muca_thermalize(muca_run *r, int64_t sweeps, void *stream)
         return rc;
     if (sweeps < 0)
         return muca_fail(MUCA_E_ARG, "sweeps must be >= 0");
-    r->stream = (hipStream_t)stream;
+    rc = muca_use_stream(r, (hipStream_t)stream);
+    if (rc)
+        return rc;
     return sweeps ? muca_enqueue_sweeps(r, sweeps, false, r->stream) : MUCA_OK;
 }
 
@@ -697,7 +733,7 @@ int muca_finish_iteration(muca_run *r, const uint64_t *H, uint64_t accepted, muc
     r->have_last = true;
     if (st)
         *st = s;
-    return muca_rebuild_thresholds(r);
+    return muca_rebuild_thresholds(r); // every merge path synchronised the stream
 }
 
 extern "C" int muca_merge_update(muca_run *r, muca_iter_stats *st)
@@ -708,6 +744,15 @@ extern "C" int muca_merge_update(muca_run *r, muca_iter_stats *st)
     if (r->pending <= 0)
         return muca_fail(MUCA_E_STATE, "merge_update without sweeps since the last merge");
     const int B = r->g.n_bins;
+    if (r->h_hist) {
+        // the histogram and the accepted-move count behind it come back through
+        // pinned memory, queued behind the sweeps: one wait per merge
+        HIP_OR_POISON(r, hipMemcpyAsync(r->h_hist, r->d_hist, (size_t)(B + 1) * 8u, hipMemcpyDeviceToHost,
+                                        r->stream));
+        HIP_OR_POISON(r, launch_fill_u64(r->d_hist, B + 1, r->stream));
+        HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
+        return muca_finish_iteration(r, r->h_hist, r->h_hist[B], st);
+    }
     std::vector<uint64_t> H(B + 1); // the histogram and the accepted-move count behind it
     HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
     HIP_OR_POISON(r, hipMemcpy(H.data(), r->d_hist, (size_t)(B + 1) * 8u, hipMemcpyDeviceToHost));

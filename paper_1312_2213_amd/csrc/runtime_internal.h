@@ -47,11 +47,21 @@ struct muca_run {
     int64_t pending = 0;           // recorded sweeps since the last merge
     bool have_last = false;
     bool poisoned = false;
+    // pinned host staging (lattice runs): the histogram and accepted-move
+    // count read back at a merge, the threshold table sent after it
+    uint64_t *h_hist = nullptr;
+    uint32_t *h_table = nullptr;
+    ~muca_run();
 };
 
 int muca_fail(int code, const char *fmt, ...);
 int muca_geometry(const muca_config *c, muca::Geometry *g);
+// Rebuilds the threshold table from lnW and queues its upload on the run's
+// stream; the caller has synchronised that stream.
 int muca_rebuild_thresholds(muca_run *r);
+// Moves the run to stream s; work still queued on its previous stream (the
+// last threshold upload included) is waited for first.
+int muca_use_stream(muca_run *r, hipStream_t s);
 int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s,
                         unsigned long long *em = nullptr, unsigned long long *hist_blocks = nullptr);
 int muca_finish_iteration(muca_run *r, const uint64_t *H, uint64_t accepted, muca_iter_stats *st);
