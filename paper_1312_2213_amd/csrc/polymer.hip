@@ -175,13 +175,25 @@ __device__ __forceinline__ void quat_rotate(double w, double x, double y, double
     oz = ((m20 * vx + m21 * vy) + m22 * vz) / n2;
 }
 
+// Pair-term cache (CACHE): the Lennard-Jones energy of every pair (a, b),
+// a < b, of the wave's chain at the current positions, in LDS at slot
+// f(a) + b with f(a) = a N - a (a + 1) / 2 - a - 1 (the upper triangle row
+// by row).  A value depends only on the two positions and the pair's
+// squared distance is the same number whichever bead is the moving one, so
+// a cached term equals a recomputed one bit for bit.
+__host__ __device__ inline int pair_row(int a, int N) { return a * N - a * (a + 1) / 2 - a - 1; }
+__host__ __device__ inline int pair_slots(int N) { return N * (N - 1) / 2; }
+
 // One chain per wavefront.  Lane j holds bead j and, with TWO (64 < N <= 128),
 // bead j + 64 (register set 1).  A pair sum slot is lane j's term plus, with
 // TWO, the term of bead j + 64.  MOVES: the paper's full move set (a
 // separate variant, so the shift-only kernel carries none of its registers).
-template <bool TWO, bool MOVES>
+// CACHE (shift moves, N <= 64 only): a move reads the old pair term from the
+// cache instead of recomputing it, and an accepted move writes the new ones.
+template <bool TWO, bool MOVES, bool CACHE>
 __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams p)
 {
+    static_assert(!CACHE || (!TWO && !MOVES), "the pair cache serves the shift-only kernel for N <= 64");
     extern __shared__ uint32_t lhist[];
     for (int i = threadIdx.x; i < a.n_bins; i += blockDim.x)
         lhist[i] = 0u;
@@ -209,6 +221,23 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
     const uint32_t B = (uint32_t)a.n_bins;
     const int up_l = (j + 1) & 63, dn_l = (j + 63) & 63;
     uint64_t nacc = 0u; // accepted moves of the recorded sweeps (wave-uniform)
+    // CACHE: the wave's pair terms; lane j's slot for the moving bead i is
+    // f(j) + i when j < i and f(i) + j when j > i
+    double *cache = nullptr;
+    int c_lo = 0;
+    if constexpr (CACHE) {
+        cache = (double *)(lhist + ((a.n_bins + 1) & ~1)) + (size_t)(threadIdx.x >> 6) * pair_slots(N);
+        c_lo = pair_row(j, N);
+        for (int k = 0; k + 2 < N; ++k) {
+            const float kx = readlane_f32(x[0].x, k), ky = readlane_f32(x[0].y, k), kz = readlane_f32(x[0].z, k);
+            if (j >= k + 2 && j < N)
+                cache[pair_row(k, N) + j] = lj_energy(p, dist2(x[0].x, x[0].y, x[0].z, kx, ky, kz));
+        }
+        // the lanes of one wave exchange terms through LDS, whose accesses
+        // from one wave complete in order; this only keeps the compiler from
+        // moving them
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
 
     for (int s_ = 0; s_ < a.n_sweeps; ++s_) {
         const uint32_t g = a.g0 + (uint32_t)s_;
@@ -278,15 +307,28 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
             const double ff_i = readlane_f64(pick(f_fwd[0], f_fwd[NS - 1]), li); // new bond (i, i + 1)
             const double ub_i = readlane_f64(pick(ub[0], ub[NS - 1]), li);       // bond (i, i + 1), before
             double t = 0.0;
+            double lnew = 0.0; // CACHE: this lane's new pair term
+            int slot = 0;
+            const bool paired = j < N && (j > i + 1 || j + 1 < i);
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 const int bd = j + 64 * s;
                 const int sep = bd > i ? bd - i : i - bd;
                 double ts = 0.0;
                 if (bd < N && sep >= 2) {
-                    const double r2n = dist2(x[s].x, x[s].y, x[s].z, nx, ny, nz);
-                    const double r2o = dist2(x[s].x, x[s].y, x[s].z, xi, yi, zi);
-                    ts = lj_energy(p, r2n) - lj_energy(p, r2o);
+                    if constexpr (CACHE) {
+                        slot = bd < i ? c_lo + i : pair_row(i, N) + bd;
+                        const double old = cache[slot];
+                        lnew = lj_energy(p, dist2(x[s].x, x[s].y, x[s].z, nx, ny, nz));
+                        // the read first, its latency covered by the new term
+                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x2, 200, 0);
+                        ts = lnew - old;
+                    } else {
+                        const double r2n = dist2(x[s].x, x[s].y, x[s].z, nx, ny, nz);
+                        const double r2o = dist2(x[s].x, x[s].y, x[s].z, xi, yi, zi);
+                        ts = lj_energy(p, r2n) - lj_energy(p, r2o);
+                    }
                 }
                 if (bd == i + 1)
                     ts = ff_i - ub_i;
@@ -317,10 +359,16 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
                     if (bd == i - 1)
                         ub[s] = fb_i;
                 }
+                if constexpr (CACHE) {
+                    if (paired)
+                        cache[slot] = lnew;
+                }
                 E = En;
                 b = bn;
                 nacc += a.record ? 1u : 0u;
             }
+            if constexpr (CACHE)
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             prev_acc = acc;
         }
         if constexpr (MOVES) {
@@ -495,6 +543,11 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
     }
 }
 
+// The cache is used when four blocks of it still fit one CU's 160 KB of
+// LDS: the occupancy the kernel without it reaches at one chain per wave
+// and four waves per SIMD.
+static bool polymer_pair_cache_fits(size_t lds_bytes) { return lds_bytes * 4u <= 160u * 1024u; }
+
 hipError_t launch_polymer_sweeps(const PolymerArgs &a, const PolymerConsts &k, hipStream_t s)
 {
     PolyParams p;
@@ -513,16 +566,18 @@ hipError_t launch_polymer_sweeps(const PolymerArgs &a, const PolymerConsts &k, h
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)(a.c_pad / chains_per_block)), block((unsigned)(64 * chains_per_block));
     const size_t lds = (size_t)a.n_bins * 4u;
+    const size_t lds_cached = (size_t)((a.n_bins + 1) & ~1) * 4u + (size_t)chains_per_block * pair_slots(a.n_beads) * 8u;
     if (a.n_beads > 64) {
         if (a.moves)
-            hipLaunchKernelGGL((polymer_sweeps<true, true>), grid, block, lds, s, a, p);
+            hipLaunchKernelGGL((polymer_sweeps<true, true, false>), grid, block, lds, s, a, p);
         else
-            hipLaunchKernelGGL((polymer_sweeps<true, false>), grid, block, lds, s, a, p);
+            hipLaunchKernelGGL((polymer_sweeps<true, false, false>), grid, block, lds, s, a, p);
+    } else if (a.moves) {
+        hipLaunchKernelGGL((polymer_sweeps<false, true, false>), grid, block, lds, s, a, p);
+    } else if (polymer_pair_cache_fits(lds_cached)) {
+        hipLaunchKernelGGL((polymer_sweeps<false, false, true>), grid, block, lds_cached, s, a, p);
     } else {
-        if (a.moves)
-            hipLaunchKernelGGL((polymer_sweeps<false, true>), grid, block, lds, s, a, p);
-        else
-            hipLaunchKernelGGL((polymer_sweeps<false, false>), grid, block, lds, s, a, p);
+        hipLaunchKernelGGL((polymer_sweeps<false, false, false>), grid, block, lds, s, a, p);
     }
     return hipGetLastError();
 }

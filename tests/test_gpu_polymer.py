@@ -62,6 +62,28 @@ def test_polymer_iterations_with_recursion():
     check_state(o, g)
 
 
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 33, 43, 44, 64])
+def test_shift_moves_sizes(N):
+    """Shift moves at sizes on both sides of the pair-term cache: with the
+    2500-bin window the cached kernel serves N <= 43 (four blocks of four
+    chains fit a CU's LDS), the recomputing kernel N = 44 .. 64.  Several
+    sweeps with a sloped weight, so that many moves are accepted and the
+    cache is rewritten between reads."""
+    print(f"shift moves N={N}", flush=True)
+    cent = -200.0 + 0.1 * (np.arange(2500) + 0.5)
+    o, g = pair(N, 67, 30 + N, lnw=-0.5 * cent)
+    for it in range(2):
+        H = o.sweeps(9)
+        o.advance(9)
+        o.merge_update(H)
+        g.run_iteration(9)
+        st = g.merge_update()
+        assert np.array_equal(g.last_hist(), H), it
+        assert np.allclose(g.lnw(), o.lnW, rtol=0, atol=1e-12), it
+        assert N == 2 or st["accept_rate"] > 0.05, st
+    check_state(o, g)
+
+
 def test_polymer_full_size_sampled():
     """The polymer workload's shape: N = 40, 4096 chains, one chain per wave."""
     cent = -200.0 + 0.1 * (np.arange(2500) + 0.5)
