@@ -110,12 +110,35 @@ __device__ __forceinline__ double from_lane_above(double v)
     return __longlong_as_double(((uint64_t)hi << 32) | lo);
 }
 
+// One level of the tree across rows (S = 32 or 16) in place: the swap moves
+// rows 2-3 (S = 32) or the odd rows (S = 16) of its first operand into the
+// second, whose own values are never read, and leaves the lanes below S of
+// the first operand as they were; the sum is valid in the lanes below S.
+template <int S>
+__device__ __forceinline__ double tree_level_swap(double t)
+{
+    const uint64_t u = __double_as_longlong(t);
+    uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+    const uint32_t junk_lo = __builtin_nondeterministic_value(lo), junk_hi = __builtin_nondeterministic_value(hi);
+    uint32_t plo, phi;
+    if constexpr (S == 32) {
+        const auto rl = __builtin_amdgcn_permlane32_swap(lo, junk_lo, false, false);
+        const auto rh = __builtin_amdgcn_permlane32_swap(hi, junk_hi, false, false);
+        lo = rl[0], plo = rl[1], hi = rh[0], phi = rh[1];
+    } else {
+        const auto rl = __builtin_amdgcn_permlane16_swap(lo, junk_lo, false, false);
+        const auto rh = __builtin_amdgcn_permlane16_swap(hi, junk_hi, false, false);
+        lo = rl[0], plo = rl[1], hi = rh[0], phi = rh[1];
+    }
+    return __longlong_as_double(((uint64_t)hi << 32) | lo) + __longlong_as_double(((uint64_t)phi << 32) | plo);
+}
+
 // The fixed summation tree over 64 slots: slot k += slot k + s for
 // s = 32, 16, ..., 1; the sum ends in lane 0.
 __device__ __forceinline__ double tree_sum(double t)
 {
-    t = t + from_lane_above<32>(t);
-    t = t + from_lane_above<16>(t);
+    t = tree_level_swap<32>(t);
+    t = tree_level_swap<16>(t);
     t = t + from_lane_above<8>(t);
     t = t + from_lane_above<4>(t);
     t = t + from_lane_above<2>(t);
@@ -188,12 +211,13 @@ __host__ __device__ inline int pair_slots(int N) { return N * (N - 1) / 2; }
 // bead j + 64 (register set 1).  A pair sum slot is lane j's term plus, with
 // TWO, the term of bead j + 64.  MOVES: the paper's full move set (a
 // separate variant, so the shift-only kernel carries none of its registers).
-// CACHE (shift moves, N <= 64 only): a move reads the old pair term from the
-// cache instead of recomputing it, and an accepted move writes the new ones.
+// CACHE (N <= 64 only): a shift or rotation reads the old pair term from the
+// cache instead of recomputing it, and an accepted move writes the new ones;
+// an accepted double bridging renumbers beads and refills the cache.
 template <bool TWO, bool MOVES, bool CACHE>
 __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams p)
 {
-    static_assert(!CACHE || (!TWO && !MOVES), "the pair cache serves the shift-only kernel for N <= 64");
+    static_assert(!CACHE || !TWO, "the pair cache serves N <= 64");
     extern __shared__ uint32_t lhist[];
     for (int i = threadIdx.x; i < a.n_bins; i += blockDim.x)
         lhist[i] = 0u;
@@ -225,18 +249,21 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
     // f(j) + i when j < i and f(i) + j when j > i
     double *cache = nullptr;
     int c_lo = 0;
-    if constexpr (CACHE) {
-        cache = (double *)(lhist + ((a.n_bins + 1) & ~1)) + (size_t)(threadIdx.x >> 6) * pair_slots(N);
-        c_lo = pair_row(j, N);
+    // every pair term at the current positions; the lanes of one wave
+    // exchange terms through LDS, whose accesses from one wave complete in
+    // order: the fence only keeps the compiler from moving them
+    auto fill_cache = [&]() {
         for (int k = 0; k + 2 < N; ++k) {
             const float kx = readlane_f32(x[0].x, k), ky = readlane_f32(x[0].y, k), kz = readlane_f32(x[0].z, k);
             if (j >= k + 2 && j < N)
                 cache[pair_row(k, N) + j] = lj_energy(p, dist2(x[0].x, x[0].y, x[0].z, kx, ky, kz));
         }
-        // the lanes of one wave exchange terms through LDS, whose accesses
-        // from one wave complete in order; this only keeps the compiler from
-        // moving them
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    };
+    if constexpr (CACHE) {
+        cache = (double *)(lhist + ((a.n_bins + 1) & ~1)) + (size_t)(threadIdx.x >> 6) * pair_slots(N);
+        c_lo = pair_row(j, N);
+        fill_cache();
     }
 
     for (int s_ = 0; s_ < a.n_sweeps; ++s_) {
@@ -412,15 +439,27 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
                 const double fr = i + 1 < N ? fene_energy(p, dist2(rx, ry, rz, nx, ny, nz), &brr) : 0.0;
                 const double ub_i = bond_of(i);
                 double t = 0.0;
+                double lnew = 0.0; // CACHE: this lane's new pair term
+                int slot = 0;
+                const bool paired = j < N && (j > i + 1 || j + 1 < i);
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     const int bd = j + 64 * s;
                     const int sep = bd > i ? bd - i : i - bd;
                     double ts = 0.0;
                     if (bd < N && sep >= 2) {
-                        const double r2n = dist2(x[s].x, x[s].y, x[s].z, nx, ny, nz);
-                        const double r2o = dist2(x[s].x, x[s].y, x[s].z, xi, yi, zi);
-                        ts = lj_energy(p, r2n) - lj_energy(p, r2o);
+                        if constexpr (CACHE) {
+                            slot = bd < i ? c_lo + i : pair_row(i, N) + bd;
+                            const double old = cache[slot];
+                            lnew = lj_energy(p, dist2(x[s].x, x[s].y, x[s].z, nx, ny, nz));
+                            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                            __builtin_amdgcn_sched_group_barrier(0x2, 200, 0);
+                            ts = lnew - old;
+                        } else {
+                            const double r2n = dist2(x[s].x, x[s].y, x[s].z, nx, ny, nz);
+                            const double r2o = dist2(x[s].x, x[s].y, x[s].z, xi, yi, zi);
+                            ts = lj_energy(p, r2n) - lj_energy(p, r2o);
+                        }
                     }
                     if (bd == i + 1)
                         ts = fr - ub_i;
@@ -448,10 +487,16 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
                         if (bd == i - 1)
                             ub[s] = fl;
                     }
+                    if constexpr (CACHE) {
+                        if (paired)
+                            cache[slot] = lnew;
+                    }
                     E = En;
                     b = bn;
                     nacc += a.record ? 1u : 0u;
                 }
+                if constexpr (CACHE)
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
             // one double bridging: bonds (bi, bi+1), (bj, bj+1) -> (bi, bj), (bi+1, bj+1)
             const Words4 w = philox4x32_10(chain, g, 0u, kTagBridge, a.k0, a.k1);
@@ -511,6 +556,8 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
                             x[s] = nxs[s];
                             ub[s] = nub[s];
                         }
+                        if constexpr (CACHE)
+                            fill_cache(); // the pair terms under the new numbering
                         E = En;
                         b = bn;
                         nacc += a.record ? 1u : 0u;
@@ -573,7 +620,10 @@ hipError_t launch_polymer_sweeps(const PolymerArgs &a, const PolymerConsts &k, h
         else
             hipLaunchKernelGGL((polymer_sweeps<true, false, false>), grid, block, lds, s, a, p);
     } else if (a.moves) {
-        hipLaunchKernelGGL((polymer_sweeps<false, true, false>), grid, block, lds, s, a, p);
+        if (polymer_pair_cache_fits(lds_cached))
+            hipLaunchKernelGGL((polymer_sweeps<false, true, true>), grid, block, lds_cached, s, a, p);
+        else
+            hipLaunchKernelGGL((polymer_sweeps<false, true, false>), grid, block, lds, s, a, p);
     } else if (polymer_pair_cache_fits(lds_cached)) {
         hipLaunchKernelGGL((polymer_sweeps<false, false, true>), grid, block, lds_cached, s, a, p);
     } else {
