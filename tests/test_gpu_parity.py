@@ -135,6 +135,30 @@ def test_two_word_rows_lane_splits_and_table_placement(model, L, layout):
             assert np.array_equal(s, o.spins) and np.array_equal(b, o.bins()), (lpc, tlds)
 
 
+def test_iterations_on_alternating_streams():
+    """The threshold table goes to the device asynchronously after each
+    merge, on the run's stream; an iteration launched on another stream (or
+    batched on one) waits for it first.  Alternating three streams and the
+    batched launch must reproduce the oracle exactly."""
+    import torch
+    from paper_1312_2213_amd import muca
+    o, g = pair("potts", 16, 300, seed=91, q=6)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.current_stream()]
+    batch = muca.Batch(max_runs=1)
+    for it in range(9):
+        H, _, _ = o.iterate(40)
+        s = streams[it % 3]
+        if it % 4 == 3:
+            batch.run_iteration([g], [40], stream=s)
+        else:
+            g.run_iteration(40, stream=s)
+        g.merge_update()
+        assert np.array_equal(g.last_hist(), H), it
+        assert close(g.lnw(), o.lnW), it
+        assert np.array_equal(g.thresholds(), o.thresholds()), it
+    assert_same_state(o, g)
+
+
 def test_chunked_iteration_equals_one_piece():
     _, a = pair("ising", 16, 64, seed=8)
     _, b = pair("ising", 16, 64, seed=8)
