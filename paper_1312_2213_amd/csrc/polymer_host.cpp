@@ -153,7 +153,12 @@ int muca_polymer_init(muca_run *r, const float *h_pos)
     r->d_table = (uint32_t *)(r->ws + g.off_table);
     r->d_hist = (unsigned long long *)(r->ws + g.off_hist);
     r->mask.assign(g.n_bins, 0);
-    r->T.assign((size_t)g.n_bins * g.n_bins, 0u);
+    try {
+        r->T.assign((size_t)g.n_bins * g.n_bins, 0u);
+    } catch (const std::bad_alloc &) {
+        return muca_fail(MUCA_E_NOMEM, "polymer init: pinned host memory for the %d x %d threshold table", g.n_bins,
+                         g.n_bins);
+    }
     hipError_t e = hipMemcpy(r->d_words, pos.data(), pos.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(r->d_energy, bond.data(), bond.size() * 8, hipMemcpyHostToDevice);
@@ -166,7 +171,7 @@ int muca_polymer_init(muca_run *r, const float *h_pos)
     if (e != hipSuccess)
         return muca_fail(MUCA_E_HIP, "polymer init: %s", hipGetErrorString(e));
     muca_polymer_build(r);
-    return muca_polymer_upload(r);
+    return muca_upload_thresholds(r);
 }
 
 // T[b][b'] = threshold of lnW(b') - lnW(b); rows built in parallel threads
@@ -189,19 +194,6 @@ void muca_polymer_build(muca_run *r)
     work(0);
     for (auto &x : th)
         x.join();
-}
-
-int muca_polymer_upload(muca_run *r)
-{
-    const int B = r->g.n_bins;
-    hipError_t e = hipMemcpyAsync(r->d_table, r->T.data(), (size_t)B * B * 4, hipMemcpyHostToDevice, r->stream);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(r->stream);
-    if (e != hipSuccess) {
-        r->poisoned = true;
-        return muca_fail(MUCA_E_HIP, "threshold upload: %s", hipGetErrorString(e));
-    }
-    return MUCA_OK;
 }
 
 int muca_polymer_enqueue(muca_run *r, int64_t sweeps, bool record, hipStream_t s)

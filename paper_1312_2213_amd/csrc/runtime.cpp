@@ -186,7 +186,10 @@ static uint32_t threshold_of(double D)
 {
     if (D >= 0.0)
         return 0xffffffffu;
-    const double v = std::ldexp(std::exp(D), 32);
+    // 2^32 e^D < 1 for D < -32 ln 2 = -22.18: the threshold is 0, no exp needed
+    if (D < -23.0)
+        return 0u;
+    const double v = std::exp(D) * 4294967296.0; // times 2^32: exact
     if (v >= 4294967295.0)
         return 0xffffffffu;
     return (uint32_t)std::floor(v);
@@ -413,31 +416,25 @@ muca_run::~muca_run()
 {
     if (h_hist)
         (void)hipHostFree(h_hist);
-    if (h_table)
-        (void)hipHostFree(h_table);
 }
 
-// The table goes out through the pinned staging buffer without a wait: the
-// next launch on the run's stream is ordered after the copy, a switch to
-// another stream waits for it, and every caller synchronised the stream
-// before, so no earlier copy still reads the staging buffer.
-static int upload_thresholds(muca_run *r)
+// The table goes out from its pinned host mirror without a wait: the next
+// launch on the run's stream is ordered after the copy, a switch to another
+// stream waits for it, and every caller synchronised the stream before it
+// rewrote the mirror, so no earlier copy still reads it.
+int muca_upload_thresholds(muca_run *r)
 {
-    if (r->g.model == kPolymer)
-        return muca_polymer_upload(r);
-    std::memcpy(r->h_table, r->T.data(), r->T.size() * 4u);
-    HIP_OR_POISON(r, hipMemcpyAsync(r->d_table, r->h_table, r->T.size() * 4u, hipMemcpyHostToDevice, r->stream));
+    HIP_OR_POISON(r, hipMemcpyAsync(r->d_table, r->T.data(), r->T.size() * 4u, hipMemcpyHostToDevice, r->stream));
     return MUCA_OK;
 }
 
 int muca_rebuild_thresholds(muca_run *r)
 {
-    if (r->g.model == kPolymer) {
+    if (r->g.model == kPolymer)
         muca_polymer_build(r);
-        return muca_polymer_upload(r);
-    }
-    build_lattice_thresholds(&r->cfg, r->g, r->lnW.data(), r->T.data());
-    return upload_thresholds(r);
+    else
+        build_lattice_thresholds(&r->cfg, r->g, r->lnW.data(), r->T.data());
+    return muca_upload_thresholds(r);
 }
 
 extern "C" int muca_init(const muca_config *c, void *d_ws, uint64_t ws_bytes, const float *h_pos,
@@ -485,9 +482,7 @@ extern "C" int muca_init(const muca_config *c, void *d_ws, uint64_t ws_bytes, co
     r->H_last.assign(g.n_bins, 0u);
     r->lnW_last.assign(g.n_bins, 0.0);
     if (g.model != kPolymer) {
-        hipError_t e = hipHostMalloc((void **)&r->h_hist, (size_t)(g.n_bins + 1) * 8u, hipHostMallocDefault);
-        if (e == hipSuccess)
-            e = hipHostMalloc((void **)&r->h_table, (size_t)g.n_bins * g.n_cols * 4u, hipHostMallocDefault);
+        const hipError_t e = hipHostMalloc((void **)&r->h_hist, (size_t)(g.n_bins + 1) * 8u, hipHostMallocDefault);
         if (e != hipSuccess) {
             delete r;
             return muca_fail(MUCA_E_HIP, "init: pinned staging: %s", hipGetErrorString(e));
@@ -503,7 +498,12 @@ extern "C" int muca_init(const muca_config *c, void *d_ws, uint64_t ws_bytes, co
         return MUCA_OK;
     }
     reachable_mask(c, g, r->mask);
-    r->T.assign((size_t)g.n_bins * g.n_cols, 0u);
+    try {
+        r->T.assign((size_t)g.n_bins * g.n_cols, 0u);
+    } catch (const std::bad_alloc &) {
+        delete r;
+        return muca_fail(MUCA_E_NOMEM, "init: pinned host memory for the threshold table");
+    }
     LatticeInitArgs a{};
     a.words = r->d_words;
     a.bins = r->d_bins;
@@ -1028,7 +1028,7 @@ extern "C" int muca_set_thresholds(muca_run *r, const uint32_t *h, int64_t count
         return muca_fail(MUCA_E_ARG, "bad arguments");
     HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
     std::memcpy(r->T.data(), h, (size_t)count * 4u);
-    return upload_thresholds(r);
+    return muca_upload_thresholds(r);
 }
 
 extern "C" int muca_get_chain_state(const muca_run *r_, int32_t chain0, int32_t count, void *state,
@@ -1092,14 +1092,14 @@ extern "C" void muca_free(muca_run *r)
 namespace {
 const uint32_t kCkptMagic = 0x4d554341u; // "MUCA"
 
-template <class T>
-void put_vec(std::vector<uint8_t> &o, const std::vector<T> &v)
+template <class V>
+void put_vec(std::vector<uint8_t> &o, const V &v)
 {
     const uint64_t n = v.size();
     const uint8_t *p = (const uint8_t *)&n;
     o.insert(o.end(), p, p + 8);
     const uint8_t *d = (const uint8_t *)v.data();
-    o.insert(o.end(), d, d + n * sizeof(T));
+    o.insert(o.end(), d, d + n * sizeof(typename V::value_type));
 }
 
 template <class T>
@@ -1216,7 +1216,7 @@ extern "C" int muca_restore(muca_run *r, const void *h_buf, uint64_t bytes)
     r->lnR = lnR;
     r->P = P;
     r->mask = mask;
-    r->T = T;
+    std::copy(T.begin(), T.end(), r->T.begin());
     r->H_last = H_last;
     r->lnW_last = lnW_last;
     return MUCA_OK;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <new>
 #include <vector>
 
 #include "../../include/muca.h"
@@ -26,6 +27,29 @@ struct Geometry {
 
 } // namespace muca
 
+// Page-locked host memory for std::vector: the host mirror of a threshold
+// table is the source of its asynchronous upload (a pageable source would be
+// staged by the runtime, synchronously).  Throws std::bad_alloc on failure.
+template <class V>
+struct PinnedAllocator {
+    using value_type = V;
+    PinnedAllocator() = default;
+    template <class U>
+    PinnedAllocator(const PinnedAllocator<U> &) {}
+    V *allocate(size_t n)
+    {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, n * sizeof(V), hipHostMallocDefault) != hipSuccess || !p)
+            throw std::bad_alloc();
+        return (V *)p;
+    }
+    void deallocate(V *p, size_t) { (void)hipHostFree(p); }
+    template <class U>
+    bool operator==(const PinnedAllocator<U> &) const { return true; }
+    template <class U>
+    bool operator!=(const PinnedAllocator<U> &) const { return false; }
+};
+
 struct muca_run {
     muca_config cfg;
     muca::Geometry g;
@@ -39,7 +63,9 @@ struct muca_run {
     double *d_energy = nullptr;    // polymer running energies
     std::vector<double> lnW, lnR, P;
     std::vector<uint8_t> mask;     // bins linked by the recursion / measured for flatness
-    std::vector<uint32_t> T;       // host mirror of the thresholds
+    // host mirror of the thresholds, the source of their asynchronous upload:
+    // rewritten only after the run's stream was synchronised
+    std::vector<uint32_t, PinnedAllocator<uint32_t>> T;
     std::vector<uint64_t> H_last;  // last merged histogram H^(n)
     std::vector<double> lnW_last;  // lnW^(n) that produced H_last
     uint32_t sweep = 0;            // global sweep counter (Philox counter word 1)
@@ -48,9 +74,8 @@ struct muca_run {
     bool have_last = false;
     bool poisoned = false;
     // pinned host staging (lattice runs): the histogram and accepted-move
-    // count read back at a merge, the threshold table sent after it
+    // count read back at a merge
     uint64_t *h_hist = nullptr;
-    uint32_t *h_table = nullptr;
     ~muca_run();
 };
 
@@ -73,7 +98,8 @@ double muca_flatness(int B, const uint8_t *m, const uint64_t *H);
 int muca_polymer_geometry(const muca_config *c, muca::Geometry *g);
 int muca_polymer_init(muca_run *r, const float *h_pos);
 void muca_polymer_build(muca_run *r);
-int muca_polymer_upload(muca_run *r);
+// queues the upload of the host threshold mirror on the run's stream
+int muca_upload_thresholds(muca_run *r);
 int muca_polymer_enqueue(muca_run *r, int64_t sweeps, bool record, hipStream_t s);
 int muca_polymer_state(muca_run *r, int32_t chain0, int32_t count, float *pos, int32_t *bins,
                        double *energy);
