@@ -11,7 +11,10 @@
  *  - Return value: MUCA_OK (0) on success, a negative muca_status otherwise;
  *    no exception crosses the ABI.  muca_last_error() returns a thread-local
  *    message for the last failure on the calling thread.
- *  - On MUCA_E_ARG / MUCA_E_RANGE / MUCA_E_NOMEM the run is left unchanged.
+ *  - On MUCA_E_ARG / MUCA_E_RANGE the run is left unchanged.  MUCA_E_NOMEM
+ *    reports a workspace that is too small (run unchanged) or host memory
+ *    (pageable or pinned) that could not be allocated; after the latter the
+ *    run may hold a partial update and should be freed.
  *    On MUCA_E_HIP the run is poisoned and later calls return MUCA_E_STATE.
  *  - Pointers named d_* are device (HBM) pointers, h_* are host pointers.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
@@ -19,7 +22,9 @@
  *    device workspace of muca_workspace_bytes() bytes (256-byte aligned) and
  *    keeps it, and the stream, alive until muca_free().  Host-side state
  *    (log weights, accumulated statistics, a mirror of the thresholds) is
- *    owned by the run handle.
+ *    owned by the run handle; the threshold mirror and the histogram
+ *    read-back buffer are page-locked host memory, so that their copies are
+ *    asynchronous on the run's stream.
  *  - A run is used from one thread at a time; distinct runs are independent.
  */
 #ifndef MUCA_H
@@ -36,7 +41,7 @@ extern "C" {
 typedef enum muca_status {
     MUCA_OK = 0,
     MUCA_E_ARG = -1,   /* invalid argument or configuration              */
-    MUCA_E_NOMEM = -2, /* workspace too small                            */
+    MUCA_E_NOMEM = -2, /* workspace too small, or host memory exhausted  */
     MUCA_E_HIP = -3,   /* a HIP runtime call failed (run poisoned)       */
     MUCA_E_STATE = -4, /* call out of order, or run poisoned             */
     MUCA_E_RANGE = -5  /* a chain is outside the binned range            */

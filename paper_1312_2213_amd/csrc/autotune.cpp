@@ -94,7 +94,7 @@ void cache_store(const std::string &path, const std::string &key, const int v[4]
 
 extern "C" int muca_autotune(const muca_config *cfg, void *d_ws, uint64_t ws_bytes, int64_t sweeps, void *stream,
                              muca_config *best, double *best_ms_per_sweep)
-{
+try {
     if (!cfg || !best || sweeps < 1)
         return muca_fail(MUCA_E_ARG, "bad arguments");
     hipStream_t s = (hipStream_t)stream;
@@ -230,3 +230,4 @@ extern "C" int muca_autotune(const muca_config *cfg, void *d_ws, uint64_t ws_byt
     }
     return rejected ? muca_fail(MUCA_OK, "%d candidates rejected", rejected) : MUCA_OK;
 }
+MUCA_ABI_CATCH

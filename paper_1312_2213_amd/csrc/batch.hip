@@ -123,16 +123,17 @@ static size_t stage_size(int max_runs, int max_items)
 }
 
 extern "C" int muca_batch_workspace_bytes(int32_t max_runs, int32_t max_items, uint64_t *bytes)
-{
+try {
     if (max_runs < 1 || max_items < 1 || !bytes)
         return muca_fail(MUCA_E_ARG, "bad arguments");
     *bytes = 256 + stage_size(max_runs, max_items);
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_batch_create(int32_t max_runs, int32_t max_items, int32_t lanes_per_chain, int32_t use_graph,
                                  void *d_ws, uint64_t ws_bytes, muca_batch **out)
-{
+try {
     if (!out)
         return muca_fail(MUCA_E_ARG, "null out");
     *out = nullptr;
@@ -176,6 +177,7 @@ extern "C" int muca_batch_create(int32_t max_runs, int32_t max_items, int32_t la
     *out = b;
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 static void drop_graph(muca_batch *b)
 {
@@ -233,7 +235,7 @@ static hipError_t enqueue_batch(muca_batch *b, int grid, size_t lds, hipStream_t
 
 extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, int32_t n, const int64_t *sweeps,
                                         void *stream)
-{
+try {
     if (!b || !runs || !sweeps || n < 1)
         return muca_fail(MUCA_E_ARG, "bad arguments");
     if (b->poisoned)
@@ -380,3 +382,4 @@ extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, in
     }
     return MUCA_OK;
 }
+MUCA_ABI_CATCH

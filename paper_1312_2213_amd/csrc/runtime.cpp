@@ -26,7 +26,8 @@
 
 using namespace muca;
 
-static thread_local std::string g_last_error;
+// fixed storage: reporting an error never allocates
+static thread_local char g_last_error[512];
 
 int muca_fail(int code, const char *fmt, ...)
 {
@@ -35,11 +36,11 @@ int muca_fail(int code, const char *fmt, ...)
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    g_last_error = buf;
+    std::memcpy(g_last_error, buf, sizeof buf);
     return code;
 }
 
-const char *muca_last_error(void) { return g_last_error.c_str(); }
+const char *muca_last_error(void) { return g_last_error; }
 
 #define HIP_OR_POISON(run, expr)                                                                   \
     do {                                                                                           \
@@ -351,7 +352,7 @@ void muca_reweight_bins(int B, const uint64_t *H, const double *lnW, const doubl
 // ---------------------------------------------------------------------------
 extern "C" int muca_config_default(int32_t model, int32_t L, int32_t q, int32_t n_chains, uint64_t seed,
                                    muca_config *c)
-{
+try {
     if (!c)
         return muca_fail(MUCA_E_ARG, "null config");
     std::memset(c, 0, sizeof *c);
@@ -390,9 +391,10 @@ extern "C" int muca_config_default(int32_t model, int32_t L, int32_t q, int32_t 
     c->step = 0.3f;
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_workspace_bytes(const muca_config *c, uint64_t *bytes)
-{
+try {
     Geometry g;
     int rc = muca_geometry(c, &g);
     if (rc)
@@ -402,6 +404,7 @@ extern "C" int muca_workspace_bytes(const muca_config *c, uint64_t *bytes)
     *bytes = g.ws_bytes;
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 static int check_run(const muca_run *r)
 {
@@ -439,7 +442,7 @@ int muca_rebuild_thresholds(muca_run *r)
 
 extern "C" int muca_init(const muca_config *c, void *d_ws, uint64_t ws_bytes, const float *h_pos,
                          void *stream, muca_run **out)
-{
+try {
     if (!out)
         return muca_fail(MUCA_E_ARG, "null out");
     *out = nullptr;
@@ -545,6 +548,7 @@ extern "C" int muca_init(const muca_config *c, void *d_ws, uint64_t ws_bytes, co
     *out = r;
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s, unsigned long long *em,
                         unsigned long long *hist_blocks)
@@ -593,7 +597,7 @@ int muca_use_stream(muca_run *r, hipStream_t s)
 }
 
 extern "C" int muca_run_iteration(muca_run *r, int64_t sweeps, void *stream)
-{
+try {
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -608,9 +612,10 @@ extern "C" int muca_run_iteration(muca_run *r, int64_t sweeps, void *stream)
     r->pending += sweeps;
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_em_shape(const muca_run *r, int32_t *n_e, int32_t *n_m)
-{
+try {
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -622,9 +627,10 @@ extern "C" int muca_em_shape(const muca_run *r, int32_t *n_e, int32_t *n_m)
         *n_m = r->g.n_bins;
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_run_iteration_em(muca_run *r, int64_t sweeps, uint64_t *d_em, void *stream)
-{
+try {
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -643,9 +649,10 @@ extern "C" int muca_run_iteration_em(muca_run *r, int64_t sweeps, uint64_t *d_em
     r->pending += sweeps;
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_blocks_shape(const muca_run *r, int32_t *n_blocks, int32_t *chains_per_block)
-{
+try {
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -658,9 +665,10 @@ extern "C" int muca_blocks_shape(const muca_run *r, int32_t *n_blocks, int32_t *
         *chains_per_block = g.cpb / g.lpc;
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_run_iteration_blocks(muca_run *r, int64_t sweeps, uint64_t *d_blocks, void *stream)
-{
+try {
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -679,9 +687,10 @@ extern "C" int muca_run_iteration_blocks(muca_run *r, int64_t sweeps, uint64_t *
     r->pending += sweeps;
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_thermalize(muca_run *r, int64_t sweeps, void *stream)
-{
+try {
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -692,6 +701,7 @@ extern "C" int muca_thermalize(muca_run *r, int64_t sweeps, void *stream)
         return rc;
     return sweeps ? muca_enqueue_sweeps(r, sweeps, false, r->stream) : MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 int muca_finish_iteration(muca_run *r, const uint64_t *H, uint64_t accepted, muca_iter_stats *st)
 {
@@ -737,7 +747,7 @@ int muca_finish_iteration(muca_run *r, const uint64_t *H, uint64_t accepted, muc
 }
 
 extern "C" int muca_merge_update(muca_run *r, muca_iter_stats *st)
-{
+try {
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -759,9 +769,10 @@ extern "C" int muca_merge_update(muca_run *r, muca_iter_stats *st)
     HIP_OR_POISON(r, launch_fill_u64(r->d_hist, B + 1, r->stream));
     return muca_finish_iteration(r, H.data(), H[B], st);
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_get_pending_hist(const muca_run *r_, uint64_t *h, int64_t n)
-{
+try {
     muca_run *r = const_cast<muca_run *>(r_);
     int rc = check_run(r);
     if (rc)
@@ -774,9 +785,10 @@ extern "C" int muca_get_pending_hist(const muca_run *r_, uint64_t *h, int64_t n)
     HIP_OR_POISON(r, hipMemcpy(h, r->d_hist, (size_t)n * 8u, hipMemcpyDeviceToHost));
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_merge_update_hist(muca_run *r, const uint64_t *h, int64_t n, muca_iter_stats *st)
-{
+try {
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -790,9 +802,10 @@ extern "C" int muca_merge_update_hist(muca_run *r, const uint64_t *h, int64_t n,
     HIP_OR_POISON(r, launch_fill_u64(r->d_hist, r->g.n_bins + 1, r->stream));
     return muca_finish_iteration(r, h, accepted, st);
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_reweight(const muca_run *r, const double *betas, int32_t n, double *out)
-{
+try {
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -820,6 +833,7 @@ extern "C" int muca_reweight(const muca_run *r, const double *betas, int32_t n, 
     }
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 // Canonical averages at beta2 from the joint histogram of a multimagnetic run
 // at beta with log weights lnW: each state's canonical weight relative to its
@@ -877,7 +891,7 @@ static void reweight_joint(int NE, int B, const uint64_t *h, const double *lnW, 
 
 extern "C" int muca_reweight_em(const muca_run *r, const uint64_t *h_em, int64_t n_em, const double *betas,
                                 int32_t n, double *out)
-{
+try {
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -896,6 +910,7 @@ extern "C" int muca_reweight_em(const muca_run *r, const uint64_t *h_em, int64_t
                        out + 6 * k);
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 // Values of the binned quantity per bin (energy; MUMA: magnetisation; Potts
 // E_unsat - 2N; polymer bin centres), as muca_reweight reports them.
@@ -916,7 +931,7 @@ static std::vector<double> bin_values(const muca_run *r)
 
 extern "C" int muca_reweight_jackknife(const muca_run *r, const uint64_t *h_blocks, int32_t n_blocks,
                                        const double *betas, int32_t n, double *out, double *err)
-{
+try {
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -969,9 +984,10 @@ extern "C" int muca_reweight_jackknife(const muca_run *r, const uint64_t *h_bloc
     }
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_sizes(const muca_run *r, int32_t *n_bins, int32_t *n_cols, int32_t *n_sites)
-{
+try {
     if (!r)
         return muca_fail(MUCA_E_ARG, "null run");
     if (n_bins)
@@ -982,33 +998,37 @@ extern "C" int muca_sizes(const muca_run *r, int32_t *n_bins, int32_t *n_cols, i
         *n_sites = r->g.n_sites;
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_get_lnw(const muca_run *r, double *h, int32_t n)
-{
+try {
     if (!r || !h || n != r->g.n_bins)
         return muca_fail(MUCA_E_ARG, "bad arguments");
     std::memcpy(h, r->lnW.data(), (size_t)n * 8u);
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_get_last_hist(const muca_run *r, uint64_t *h, int32_t n)
-{
+try {
     if (!r || !h || n != r->g.n_bins)
         return muca_fail(MUCA_E_ARG, "bad arguments");
     std::memcpy(h, r->H_last.data(), (size_t)n * 8u);
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_get_thresholds(const muca_run *r, uint32_t *h, int64_t count)
-{
+try {
     if (!r || !h || count != (int64_t)r->T.size())
         return muca_fail(MUCA_E_ARG, "bad arguments");
     std::memcpy(h, r->T.data(), (size_t)count * 4u);
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_set_lnw(muca_run *r, const double *h, int32_t n)
-{
+try {
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -1018,9 +1038,10 @@ extern "C" int muca_set_lnw(muca_run *r, const double *h, int32_t n)
     r->lnW.assign(h, h + n);
     return muca_rebuild_thresholds(r);
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_set_thresholds(muca_run *r, const uint32_t *h, int64_t count)
-{
+try {
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -1030,10 +1051,11 @@ extern "C" int muca_set_thresholds(muca_run *r, const uint32_t *h, int64_t count
     std::memcpy(r->T.data(), h, (size_t)count * 4u);
     return muca_upload_thresholds(r);
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_get_chain_state(const muca_run *r_, int32_t chain0, int32_t count, void *state,
                                     int32_t *bins, double *energy)
-{
+try {
     muca_run *r = const_cast<muca_run *>(r_);
     int rc = check_run(r);
     if (rc)
@@ -1076,6 +1098,7 @@ extern "C" int muca_get_chain_state(const muca_run *r_, int32_t chain0, int32_t 
     }
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" void muca_free(muca_run *r)
 {
@@ -1138,7 +1161,7 @@ struct Reader {
 } // namespace
 
 extern "C" int muca_checkpoint(const muca_run *r_, void *h_buf, uint64_t *bytes)
-{
+try {
     muca_run *r = const_cast<muca_run *>(r_);
     int rc = check_run(r);
     if (rc)
@@ -1176,9 +1199,10 @@ extern "C" int muca_checkpoint(const muca_run *r_, void *h_buf, uint64_t *bytes)
     *bytes = total;
     return MUCA_OK;
 }
+MUCA_ABI_CATCH
 
 extern "C" int muca_restore(muca_run *r, const void *h_buf, uint64_t bytes)
-{
+try {
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -1221,3 +1245,4 @@ extern "C" int muca_restore(muca_run *r, const void *h_buf, uint64_t bytes)
     r->lnW_last = lnW_last;
     return MUCA_OK;
 }
+MUCA_ABI_CATCH

@@ -80,6 +80,18 @@ struct muca_run {
 };
 
 int muca_fail(int code, const char *fmt, ...);
+
+// Handlers of a C entry point's function-try-block: no exception crosses the
+// ABI (host allocations are the only source: std::bad_alloc).
+#define MUCA_ABI_CATCH                                                                                 \
+    catch (const std::bad_alloc &)                                                                     \
+    {                                                                                                  \
+        return muca_fail(MUCA_E_NOMEM, "out of host memory");                                          \
+    }                                                                                                  \
+    catch (...)                                                                                        \
+    {                                                                                                  \
+        return muca_fail(MUCA_E_STATE, "unexpected exception in the library");                       \
+    }
 int muca_geometry(const muca_config *c, muca::Geometry *g);
 // Rebuilds the threshold table from lnW and queues its upload on the run's
 // stream; the caller has synchronised that stream.
