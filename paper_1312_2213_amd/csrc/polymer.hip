@@ -73,6 +73,16 @@ __device__ __forceinline__ double dist2(float ax, float ay, float az, float bx, 
     return dx * dx + dy * dy + dz * dz;
 }
 
+// The same squared distance with the first position already in FP64 (a
+// float converts to double exactly).
+__device__ __forceinline__ double dist2d(double ax, double ay, double az, float bx, float by, float bz)
+{
+    const double dx = ax - (double)bx;
+    const double dy = ay - (double)by;
+    const double dz = az - (double)bz;
+    return dx * dx + dy * dy + dz * dz;
+}
+
 __device__ __forceinline__ double readlane_f64(double v, int lane)
 {
     const uint64_t u = __double_as_longlong(v);
@@ -231,11 +241,26 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
     float4 *pos = a.pos + (size_t)c * SLOTS;
     double *bond = a.bond + (size_t)c * SLOTS;
     float4 x[NS];
+    // the shift-only kernel for N <= 64 also keeps x in FP64 for the pair
+    // distances (the other variants have no registers to spare for it)
+    constexpr bool XD = !TWO && !MOVES;
+    double xd[NS], yd[NS], zd[NS];
+    auto own_d2 = [&](int s, float bx, float by, float bz) {
+        if constexpr (XD)
+            return dist2d(xd[s], yd[s], zd[s], bx, by, bz);
+        else
+            return dist2(x[s].x, x[s].y, x[s].z, bx, by, bz);
+    };
+    auto set_xd = [&](int s) {
+        if constexpr (XD)
+            xd[s] = x[s].x, yd[s] = x[s].y, zd[s] = x[s].z;
+    };
     double ub[NS]; // energy of bond (bead, bead + 1)
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int bd = j + 64 * s;
         x[s] = bd < N ? pos[bd] : make_float4(0.f, 0.f, 0.f, 0.f);
+        set_xd(s);
         ub[s] = bd < N - 1 ? bond[bd] : 0.0;
     }
     double E = a.energy[c];
@@ -256,7 +281,7 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
         for (int k = 0; k + 2 < N; ++k) {
             const float kx = readlane_f32(x[0].x, k), ky = readlane_f32(x[0].y, k), kz = readlane_f32(x[0].z, k);
             if (j >= k + 2 && j < N)
-                cache[pair_row(k, N) + j] = lj_energy(p, dist2(x[0].x, x[0].y, x[0].z, kx, ky, kz));
+                cache[pair_row(k, N) + j] = lj_energy(p, own_d2(0, kx, ky, kz));
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     };
@@ -346,14 +371,14 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
                     if constexpr (CACHE) {
                         slot = bd < i ? c_lo + i : pair_row(i, N) + bd;
                         const double old = cache[slot];
-                        lnew = lj_energy(p, dist2(x[s].x, x[s].y, x[s].z, nx, ny, nz));
+                        lnew = lj_energy(p, own_d2(s, nx, ny, nz));
                         // the read first, its latency covered by the new term
                         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
                         __builtin_amdgcn_sched_group_barrier(0x2, 200, 0);
                         ts = lnew - old;
                     } else {
-                        const double r2n = dist2(x[s].x, x[s].y, x[s].z, nx, ny, nz);
-                        const double r2o = dist2(x[s].x, x[s].y, x[s].z, xi, yi, zi);
+                        const double r2n = own_d2(s, nx, ny, nz);
+                        const double r2o = own_d2(s, xi, yi, zi);
                         ts = lj_energy(p, r2n) - lj_energy(p, r2o);
                     }
                 }
@@ -380,6 +405,7 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
                         x[s].x = nx;
                         x[s].y = ny;
                         x[s].z = nz;
+                        set_xd(s);
                         if (i + 1 < N)
                             ub[s] = ff_i;
                     }
@@ -451,13 +477,13 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
                         if constexpr (CACHE) {
                             slot = bd < i ? c_lo + i : pair_row(i, N) + bd;
                             const double old = cache[slot];
-                            lnew = lj_energy(p, dist2(x[s].x, x[s].y, x[s].z, nx, ny, nz));
+                            lnew = lj_energy(p, own_d2(s, nx, ny, nz));
                             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
                             __builtin_amdgcn_sched_group_barrier(0x2, 200, 0);
                             ts = lnew - old;
                         } else {
-                            const double r2n = dist2(x[s].x, x[s].y, x[s].z, nx, ny, nz);
-                            const double r2o = dist2(x[s].x, x[s].y, x[s].z, xi, yi, zi);
+                            const double r2n = own_d2(s, nx, ny, nz);
+                            const double r2o = own_d2(s, xi, yi, zi);
                             ts = lj_energy(p, r2n) - lj_energy(p, r2o);
                         }
                     }
@@ -481,6 +507,7 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
                             x[s].x = nx;
                             x[s].y = ny;
                             x[s].z = nz;
+                            set_xd(s);
                             if (i + 1 < N)
                                 ub[s] = fr;
                         }
@@ -554,6 +581,7 @@ __global__ __launch_bounds__(256) void polymer_sweeps(PolymerArgs a, PolyParams 
 #pragma unroll
                         for (int s = 0; s < NS; ++s) {
                             x[s] = nxs[s];
+                            set_xd(s);
                             ub[s] = nub[s];
                         }
                         if constexpr (CACHE)
