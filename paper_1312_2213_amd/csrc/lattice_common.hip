@@ -85,6 +85,17 @@ __global__ void fill_u64(unsigned long long *p, int64_t n)
         p[i] = 0ull;
 }
 
+// Moves n counters to (page-locked, device-visible) host memory and clears
+// them: a merge's read-back and reset in one dispatch.
+__global__ void drain_u64(unsigned long long *p, unsigned long long *host, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        host[i] = p[i];
+        p[i] = 0ull;
+    }
+}
+
 
 bool lattice_size_supported(int L)
 {
@@ -107,6 +118,15 @@ hipError_t launch_lattice_init(const LatticeInitArgs &a, hipStream_t s)
 {
     const int block = 64;
     hipLaunchKernelGGL(lattice_init, dim3((a.c_pad + block - 1) / block), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_drain_u64(unsigned long long *p, unsigned long long *host, int64_t n, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const int block = 256;
+    hipLaunchKernelGGL(drain_u64, dim3((unsigned)((n + block - 1) / block)), dim3(block), 0, s, p, host, n);
     return hipGetLastError();
 }
 

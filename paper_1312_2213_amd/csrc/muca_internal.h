@@ -88,6 +88,8 @@ hipError_t launch_lattice_init(const LatticeInitArgs &a, hipStream_t s);
 hipError_t launch_lattice_sweeps(int model, int L, int layout, int lpc, int threads, const LatticeArgs &a,
                                  hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t s);
+// host: device address of page-locked host memory (hipHostGetDevicePointer)
+hipError_t launch_drain_u64(unsigned long long *p, unsigned long long *host, int64_t n, hipStream_t s);
 bool lattice_size_supported(int L);
 
 } // namespace muca

@@ -485,7 +485,11 @@ try {
     r->H_last.assign(g.n_bins, 0u);
     r->lnW_last.assign(g.n_bins, 0.0);
     if (g.model != kPolymer) {
-        const hipError_t e = hipHostMalloc((void **)&r->h_hist, (size_t)(g.n_bins + 1) * 8u, hipHostMallocDefault);
+        // coherent: the merge's drain kernel writes it directly
+        hipError_t e = hipHostMalloc((void **)&r->h_hist, (size_t)(g.n_bins + 1) * 8u,
+                                     hipHostMallocMapped | hipHostMallocCoherent);
+        if (e == hipSuccess)
+            e = hipHostGetDevicePointer((void **)&r->h_hist_dev, r->h_hist, 0);
         if (e != hipSuccess) {
             delete r;
             return muca_fail(MUCA_E_HIP, "init: pinned staging: %s", hipGetErrorString(e));
@@ -755,11 +759,10 @@ try {
         return muca_fail(MUCA_E_STATE, "merge_update without sweeps since the last merge");
     const int B = r->g.n_bins;
     if (r->h_hist) {
-        // the histogram and the accepted-move count behind it come back through
-        // pinned memory, queued behind the sweeps: one wait per merge
-        HIP_OR_POISON(r, hipMemcpyAsync(r->h_hist, r->d_hist, (size_t)(B + 1) * 8u, hipMemcpyDeviceToHost,
-                                        r->stream));
-        HIP_OR_POISON(r, launch_fill_u64(r->d_hist, B + 1, r->stream));
+        // the histogram and the accepted-move count behind it are written to
+        // pinned host memory and cleared by one kernel queued behind the
+        // sweeps: one dispatch and one wait per merge
+        HIP_OR_POISON(r, launch_drain_u64(r->d_hist, r->h_hist_dev, B + 1, r->stream));
         HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
         return muca_finish_iteration(r, r->h_hist, r->h_hist[B], st);
     }

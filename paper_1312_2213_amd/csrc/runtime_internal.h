@@ -74,8 +74,9 @@ struct muca_run {
     bool have_last = false;
     bool poisoned = false;
     // pinned host staging (lattice runs): the histogram and accepted-move
-    // count read back at a merge
+    // count read back at a merge, and its device-side address
     uint64_t *h_hist = nullptr;
+    unsigned long long *h_hist_dev = nullptr;
     ~muca_run();
 };
 
