@@ -15,7 +15,8 @@ region.  The line also carries:
                 time of one persistent hipGraph launch per round against the
                 same instances run one after another with plain launches.
 
-Other modes (--workload): "batched" (time to flat, batched vs plain),
+Other modes (--workload): "ising64_flat" (the same configuration run to a
+flat histogram: time to flat), "batched" (time to flat, batched vs plain),
 "serving" (200 Poisson requests, p50/p99 time to flat), "polymer" (N = 40,
 4096 chains), "polymer_paper" (the paper's homopolymer, N = 40 and 80),
 "speedup" (statistical speedup S*_p over chains per run, Eq. 6; with
@@ -52,8 +53,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ising64",
-                    choices=["ising64", "batched", "serving", "polymer", "polymer_paper", "speedup", "muma_em",
-                             "copy"])
+                    choices=["ising64", "ising64_flat", "batched", "serving", "polymer", "polymer_paper", "speedup",
+                             "muma_em", "copy"])
     ap.add_argument("--sweeps", type=int, default=10000, help="sweeps per iteration (workload: 10^4)")
     ap.add_argument("--lanes-per-chain", type=int, default=0)
     ap.add_argument("--batch-lanes-per-chain", type=int, default=0, help="batched runs: 4, 16 or 0 (per run)")
@@ -210,6 +211,44 @@ def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int =
                     "mean_time_to_flat_batched_s": sum(ttf_b) / len(ttf_b),
                     "mean_time_to_flat_plain_s": sum(ttf_p) / len(ttf_p)})
     return out
+
+
+def bench_ising64_flat(args):
+    """The headline configuration run to a flat histogram: Ising L = 64,
+    bit-packed, 4096 chains, seed 2, 10^4 sweeps per iteration, lnW = 0 at
+    the start, iterations until min(H)/mean(H) > 0.5 over the reachable bins
+    of E in [-8192, 8192] (or the iteration cap).  Time to flat = wall time
+    from the first launch to the end of the flat merge."""
+    import torch
+    from paper_1312_2213_amd import muca
+
+    torch.cuda.set_device(0)
+    L, C, seed, S = 64, 4096, 2, args.sweeps
+    cap = args.max_iters or 700
+    cfg = muca.muca_config_default("ising", L, 2, C, seed, layout=muca.MUCA_LAYOUT_BIT,
+                                   lanes_per_chain=args.lanes_per_chain)
+    stream = torch.cuda.current_stream()
+    run = muca.Run(cfg, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n, st = 0, None
+    while n < cap:
+        run.run_iteration(S)
+        st = run.merge_update()
+        n += 1
+        print(f"iteration {n}: flatness {st['flatness']:.3f}, visited [{st['lo_visited']}, {st['hi_visited']}], "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        if st["flat"]:
+            break
+    dt = time.perf_counter() - t0
+    attempts = C * L * L * S * n
+    return {"metric": "time-to-flat-histogram (plain MUCA, 1 GPU)", "value": dt, "unit": "s",
+            "higher_is_better": False, "flat": bool(st["flat"]), "iterations": n,
+            "attempts_per_s": attempts / dt, "final_flatness": st["flatness"],
+            "visited": [st["lo_visited"], st["hi_visited"]], "n_gpus": 1, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "plain MUCA 2D Ising L=64 periodic, bit-packed spins, 4096 chains, seed 2, "
+                                   f"{S} sweeps per iteration, bins E in [-8192, 8192] step 4, flatness 0.5, "
+                                   f"cap {cap} iterations"}}
 
 
 def bench_ising64(args):
@@ -485,9 +524,11 @@ def main():
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
         sys.exit(2)
     if args.max_iters is None:
-        args.max_iters = {"serving": 3000, "speedup": 1000, "muma_em": 1000}.get(args.workload, 40)
+        args.max_iters = {"serving": 3000, "speedup": 1000, "muma_em": 1000, "ising64_flat": 700}.get(args.workload, 40)
     if args.workload == "ising64":
         out = bench_ising64(args)
+    elif args.workload == "ising64_flat":
+        out = bench_ising64_flat(args)
     elif args.workload == "batched":
         out = batched_vs_plain(args.batched_rounds, max_iters=args.max_iters, batch_lpc=args.batch_lanes_per_chain)
     elif args.workload == "serving":
