@@ -47,6 +47,19 @@ __host__ __device__ constexpr int variant_index(int kind, int li, int tlds, int 
     return ((kind * 6 + li) * 2 + tlds) * 2 + lpc16;
 }
 
+// The descriptor's values are the same for the whole workgroup, but inside a
+// non-inlined function the compiler cannot know it: read them through
+// readfirstlane, so that the sweep loop, the key schedule and the addresses
+// stay on the scalar unit as in the plain kernel.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+template <class T>
+__device__ __forceinline__ T *uni(T *p)
+{
+    const uint64_t v = (uint64_t)p;
+    return (T *)(((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v));
+}
+
 template <int V>
 __device__ __noinline__ void run_variant(const BatchDesc *d, int c_first)
 {
@@ -59,8 +72,20 @@ __device__ __noinline__ void run_variant(const BatchDesc *d, int c_first)
     constexpr int MODEL = kind <= 1 ? kIsing : (kind <= 3 ? kMuma : kPotts);
     constexpr int LAYOUT = (kind == 0 || kind == 2) ? kLayoutBit : kLayoutByte;
     constexpr int LPC = lpc16 ? 16 : 4;
-    const LatticeArgs a = d->a;
-    sweep_block<MODEL, L, LAYOUT, TLDS, LPC>(a, c_first, smem);
+    const LatticeArgs v = d->a;
+    LatticeArgs a;
+    a.words = uni(v.words);
+    a.bins = uni(v.bins);
+    a.thresholds = uni(v.thresholds);
+    a.hist = uni(v.hist);
+    a.k0 = uni(v.k0), a.k1 = uni(v.k1), a.g0 = uni(v.g0);
+    a.n_sweeps = uni(v.n_sweeps), a.n_chains = uni(v.n_chains), a.c_pad = uni(v.c_pad);
+    a.n_bins = uni(v.n_bins), a.q = uni(v.q), a.record = uni(v.record), a.table_in_lds = uni(v.table_in_lds);
+    a.chain0 = uni(v.chain0);
+    a.em = uni(v.em);
+    a.accepts = uni(v.accepts);
+    a.hist_blocks = uni(v.hist_blocks);
+    sweep_block<MODEL, L, LAYOUT, TLDS, LPC>(a, uni(c_first), smem);
 }
 
 template <int... V>

@@ -189,6 +189,23 @@ constexpr int32_t row_origin() { return MODEL == kIsing ? 4 : 8; }
 
 typedef __attribute__((address_space(3))) const uint32_t lds_u32;
 
+// Lattice words, bins and global threshold tables are global memory.  Typed
+// as such, their loads and stores are global (not flat) operations also where
+// the sweep runs inside a non-inlined function (the batched launch), whose
+// pointer arguments the compiler cannot place: a flat operation counts
+// against the LDS wait counter, which the site loop waits on for its
+// threshold reads.
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) int32_t gi32;
+typedef __attribute__((address_space(1))) uint8_t gu8;
+typedef __attribute__((address_space(1))) unsigned long long gu64;
+
+// Relaxed device-scope add to a global 64-bit counter.
+__device__ __forceinline__ void gadd(gu64 *p, unsigned long long v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Threshold at `addr`: an absolute LDS byte address when the table is staged
 // in LDS, else a byte offset from the global table.
 template <bool TLDS>
@@ -197,7 +214,7 @@ __device__ __forceinline__ uint32_t load_t(const uint32_t *__restrict__ T, int32
     if constexpr (TLDS)
         return *(lds_u32 *)(uintptr_t)(uint32_t)addr;
     else
-        return *(const uint32_t *)((const char *)T + addr);
+        return *(const gu32 *)((uintptr_t)T + (intptr_t)addr);
 }
 
 // Byte shift of the row origin when a site with nmis4 = 4 x misaligned
@@ -540,7 +557,7 @@ __device__ __forceinline__ uint32_t pair_mis(const uint32_t (&A)[Row1<L>::W], co
 // Storage <-> packed row.  BYTE storage holds int8 +1 (0x01) / -1 (0xFF),
 // four sites per word; bit 1 of a byte is set exactly for -1.
 template <int L, int LAYOUT>
-__device__ __forceinline__ void load_row(const uint32_t *base, size_t stride, int y, uint32_t (&R)[Row1<L>::W])
+__device__ __forceinline__ void load_row(const gu32 *base, size_t stride, int y, uint32_t (&R)[Row1<L>::W])
 {
     constexpr int W = Row1<L>::W;
     if constexpr (LAYOUT == kLayoutBit) {
@@ -562,7 +579,7 @@ __device__ __forceinline__ void load_row(const uint32_t *base, size_t stride, in
 }
 
 template <int L, int LAYOUT>
-__device__ __forceinline__ void store_row(uint32_t *base, size_t stride, int y, const uint32_t (&R)[Row1<L>::W])
+__device__ __forceinline__ void store_row(gu32 *base, size_t stride, int y, const uint32_t (&R)[Row1<L>::W])
 {
     constexpr int W = Row1<L>::W;
     if constexpr (LAYOUT == kLayoutBit) {
@@ -649,22 +666,23 @@ __device__ __forceinline__ void potts_row(const uint32_t (&up)[W], uint32_t (&cu
 
 // Adds the block's packed LDS counters to the global histogram and clears
 // them.  Called by every thread of the block between two barriers.
-__device__ __forceinline__ void flush_hist(uint32_t *lhist, int hw, unsigned long long *hist,
-                                           unsigned long long *blk = nullptr)
+__device__ __forceinline__ void flush_hist(uint32_t *lhist, int hw, unsigned long long *hist_,
+                                           gu64 *blk = nullptr)
 {
+    gu64 *hist = (gu64 *)hist_;
     for (int i = threadIdx.x; i < hw; i += blockDim.x) {
         const uint32_t v = lhist[i];
         if (v) {
             lhist[i] = 0u;
             if (v & 0xFFFFu)
-                atomicAdd(&hist[2 * i], (unsigned long long)(v & 0xFFFFu));
+                gadd(&hist[2 * i], (unsigned long long)(v & 0xFFFFu));
             if (v >> 16)
-                atomicAdd(&hist[2 * i + 1], (unsigned long long)(v >> 16));
+                gadd(&hist[2 * i + 1], (unsigned long long)(v >> 16));
             if (blk) { // this block's own histogram, for jackknife errors
                 if (v & 0xFFFFu)
-                    atomicAdd(&blk[2 * i], (unsigned long long)(v & 0xFFFFu));
+                    gadd(&blk[2 * i], (unsigned long long)(v & 0xFFFFu));
                 if (v >> 16)
-                    atomicAdd(&blk[2 * i + 1], (unsigned long long)(v >> 16));
+                    gadd(&blk[2 * i + 1], (unsigned long long)(v >> 16));
             }
         }
     }
@@ -693,7 +711,7 @@ __device__ __forceinline__ void flush_hist(uint32_t *lhist, int hw, unsigned lon
 __device__ __forceinline__ void flush_accepts(const LatticeArgs &a, bool counts, uint32_t &nacc)
 {
     if (counts && a.accepts && nacc)
-        atomicAdd(a.accepts, (unsigned long long)nacc);
+        gadd((gu64 *)a.accepts, (unsigned long long)nacc);
     nacc = 0u;
 }
 
@@ -732,7 +750,7 @@ struct PottsLP {
 
 // Segment of row y owned by lane j: sites [S j, S j + S) in bytes 0..S-1.
 template <int L, int LPC>
-__device__ __forceinline__ void lp_load(const uint32_t *base, size_t stride, int y, uint32_t j,
+__device__ __forceinline__ void lp_load(const gu32 *base, size_t stride, int y, uint32_t j,
                                         uint32_t (&seg)[PottsLP<L, LPC>::SW])
 {
     constexpr int S = PottsLP<L, LPC>::S, SW = PottsLP<L, LPC>::SW, W = L / 4;
@@ -755,7 +773,7 @@ __device__ __forceinline__ void lp_load(const uint32_t *base, size_t stride, int
 }
 
 template <int L, int LPC>
-__device__ __forceinline__ void lp_store(uint32_t *base, size_t stride, int y, uint32_t j,
+__device__ __forceinline__ void lp_store(gu32 *base, size_t stride, int y, uint32_t j,
                                          const uint32_t (&seg)[PottsLP<L, LPC>::SW])
 {
     constexpr int S = PottsLP<L, LPC>::S, SW = PottsLP<L, LPC>::SW, W = L / 4;
@@ -768,7 +786,7 @@ __device__ __forceinline__ void lp_store(uint32_t *base, size_t stride, int y, u
 #pragma unroll
         for (int m = 0; m < S; ++m) {
             const uint32_t bb = b0 + (uint32_t)m;
-            uint8_t *p = (uint8_t *)(base + ((size_t)y * W + (bb >> 2)) * stride) + (bb & 3u);
+            gu8 *p = (gu8 *)(base + ((size_t)y * W + (bb >> 2)) * stride) + (bb & 3u);
             *p = (uint8_t)(seg[m / 4] >> (8 * (m % 4)));
         }
     }
@@ -900,10 +918,10 @@ __device__ __forceinline__ void lp_row(const uint64_t (&geo)[PottsLP<L, LPC>::S]
 // The sweeps of one chain (per lane: its segment), with the histogram
 // bookkeeping of sweep_block.
 template <int L, int LPC, bool TLDS>
-__device__ __forceinline__ int32_t potts_lp_sweeps(const LatticeArgs &a, uint32_t *base, size_t stride,
+__device__ __forceinline__ int32_t potts_lp_sweeps(const LatticeArgs &a, gu32 *base, size_t stride,
                                                    uint32_t chain, uint32_t j, bool counts, int32_t b,
                                                    const uint32_t *__restrict__ T, int32_t tbase, uint32_t *lhist,
-                                                   int hw, int flush_every, unsigned long long *blk)
+                                                   int hw, int flush_every, gu64 *blk)
 {
     using P = PottsLP<L, LPC>;
     constexpr int S = P::S, SW = P::SW, NCALL = P::NCALL, KC = L / 2; // Philox calls per row
@@ -1069,7 +1087,7 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
                 const int bb = i >> 3, cc = i & 7;
                 src = bb * 9 + (cc == 4 ? 8 : cc);
             }
-            smem[i] = a.thresholds[src];
+            smem[i] = ((const gu32 *)a.thresholds)[src];
         }
         T = smem;
     }
@@ -1078,17 +1096,17 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
     const int c = c_first + tid / LPC;       // chain of this lane
     const uint32_t j = (uint32_t)(tid % LPC); // rank within the chain's lane group
     const bool leader = j == 0u;
-    uint32_t *base = a.words + c;
+    gu32 *base = (gu32 *)a.words + c;
     const size_t stride = (size_t)a.c_pad;
     const uint32_t chain = (uint32_t)(a.chain0 + c);
     const bool counts = a.record && c < a.n_chains && leader;
-    int32_t b = a.bins[c];
+    int32_t b = ((const gi32 *)a.bins)[c];
     // sweeps between two flushes of the 16-bit LDS counters
     const int flush_every = kMaxBlockCount / (int)(blockDim.x / LPC);
     int until_flush = flush_every;
     // this block's histogram (plain launches with per-block histograms)
-    unsigned long long *blk =
-        a.hist_blocks ? a.hist_blocks + (size_t)(c_first / (int)(blockDim.x / LPC)) * (size_t)a.n_bins : nullptr;
+    gu64 *blk = a.hist_blocks ? (gu64 *)a.hist_blocks + (size_t)(c_first / (int)(blockDim.x / LPC)) * (size_t)a.n_bins
+                              : nullptr;
 
     if constexpr (MODEL == kPotts && PottsLP<L, LPC>::ok) {
         int32_t tbase = 0;
@@ -1208,7 +1226,7 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
                 if constexpr (MODEL == kMuma) {
                     if (em) { // E = -2N + 2 nmis = -2N + 4 e, e <= N
                         const uint32_t e = min(nmis >> 1, (uint32_t)(L * L));
-                        atomicAdd(&a.em[(size_t)e * (size_t)a.n_bins + (size_t)bb], 1ull);
+                        gadd((gu64 *)a.em + (size_t)e * (size_t)a.n_bins + (size_t)bb, 1ull);
                     }
                 }
             }
@@ -1226,7 +1244,7 @@ __device__ __forceinline__ void sweep_block(const LatticeArgs &a, int c_first, u
         b = (((rowb - tbase) >> 2) - row_origin<MODEL>()) / NC;
     }
     if (leader)
-        a.bins[c] = b;
+        ((gi32 *)a.bins)[c] = b;
     __syncthreads();
     flush_hist(lhist, hw, a.hist, blk);
 }
