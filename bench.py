@@ -133,6 +133,9 @@ def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int =
                 r.run_iteration(sw, stream=stream)
                 st = r.merge_update()
                 n += 1
+                if n % 500 == 0:
+                    print(f"plain: instance {len(iters)}, iteration {n}, flatness {st['flatness']:.3f}",
+                          file=sys.stderr, flush=True)
                 if max_iters is None:
                     if n >= rounds:
                         break
@@ -140,6 +143,8 @@ def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int =
                     break
             ttf.append(time.perf_counter() - t0)
             iters.append(n)
+            print(f"plain: instance {len(iters) - 1} done after {n} iterations, {ttf[-1]:.1f} s",
+                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, ttf, iters, runs
 
@@ -163,9 +168,13 @@ def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int =
                 done = n[k] >= rounds if max_iters is None else (st["flat"] or n[k] >= max_iters)
                 if done:
                     ttf[k] = time.perf_counter() - t0
+                    print(f"batched: instance {k} done after {n[k]} iterations, {ttf[k]:.1f} s",
+                          file=sys.stderr, flush=True)
                 else:
                     nxt.append(k)
             live = nxt
+            if live and max(n) % 500 == 0:
+                print(f"batched: round {max(n)}, {len(live)} instances left", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         run_batched.flat = flat
         return time.perf_counter() - t0, ttf, n, runs
@@ -183,8 +192,14 @@ def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int =
             reqs.append(Request(id=k, arrival=0.0, model="lattice", L=c.L, q=c.q, chains=c.n_chains,
                                 seed=c.seed, max_iters=rounds if max_iters is None else max_iters,
                                 sweeps_per_iter=sw, cfg=cfg))
+        def tick(rounds, n_active):
+            if rounds % 2000 == 0:
+                print(f"served: round {rounds}, {n_active} instances left", file=sys.stderr, flush=True)
+
         srv = Server(hbm_budget=1 << 40, chain_slots=1 << 20, lanes_per_chain=batch_lpc,
-                     keep_results=True, stream=stream)
+                     keep_results=True, stream=stream, on_round=tick,
+                     log=lambda r: print(f"served: instance {r.id} done after {r.iterations} iterations, "
+                                         f"{r.finished:.1f} s", file=sys.stderr, flush=True))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = srv.serve(reqs, realtime=False)

@@ -88,7 +88,7 @@ class _Active:
 class Server:
     def __init__(self, hbm_budget: int = 64 << 20, chain_slots: int = 1 << 16,
                  round_site_updates: int = 1 << 16, lanes_per_chain: int = 0, use_graph: bool = True,
-                 max_active: int = 256, keep_results: bool = False, stream=None, log=None):
+                 max_active: int = 256, keep_results: bool = False, stream=None, log=None, on_round=None):
         import torch
         self.hbm_budget = hbm_budget
         self.chain_slots = chain_slots
@@ -99,6 +99,7 @@ class Server:
                                 use_graph=use_graph)
         self.max_active = max_active
         self.log = log  # called with each Result as its request retires
+        self.on_round = on_round  # called with (rounds so far, active requests) after each round
         self.rounds = 0
         self.peak_active = 0
         self.peak_mem = 0
@@ -176,6 +177,8 @@ class Server:
                 else:
                     still.append(a)
             active = still
+            if self.on_round:
+                self.on_round(self.rounds, len(active))
         torch.cuda.synchronize()
         return [results[r.id] for r in sorted(requests, key=lambda r: r.id)]
 
