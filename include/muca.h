@@ -18,6 +18,10 @@
  *    On MUCA_E_HIP the run is poisoned and later calls return MUCA_E_STATE.
  *  - Pointers named d_* are device (HBM) pointers, h_* are host pointers.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    A run's device work (sweeps, the threshold upload that follows every
+ *    merge) is ordered on the stream of its last call; a call on another
+ *    stream first waits for the previous stream, so runs may move between
+ *    streams freely.  Calls that overlap on one run are not allowed.
  *  - The library never allocates or frees device memory: the caller passes a
  *    device workspace of muca_workspace_bytes() bytes (256-byte aligned) and
  *    keeps it, and the stream, alive until muca_free().  Host-side state
