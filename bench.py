@@ -57,6 +57,7 @@ def parse():
                              "muma_em", "copy"])
     ap.add_argument("--sweeps", type=int, default=10000, help="sweeps per iteration (workload: 10^4)")
     ap.add_argument("--lanes-per-chain", type=int, default=0)
+    ap.add_argument("--chains", type=int, default=4096, help="ising64: chains (workload: 4096)")
     ap.add_argument("--batch-lanes-per-chain", type=int, default=0, help="batched runs: 4, 16 or 0 (per run)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -271,7 +272,7 @@ def bench_ising64(args):
     from paper_1312_2213_amd import muca
 
     torch.cuda.set_device(0)
-    L, C, seed, S = 64, 4096, 2, args.sweeps
+    L, C, seed, S = 64, args.chains, 2, args.sweeps
     cfg = muca.muca_config_default("ising", L, 2, C, seed, layout=muca.MUCA_LAYOUT_BIT,
                                    lanes_per_chain=args.lanes_per_chain)
     stream = torch.cuda.current_stream()
@@ -301,7 +302,7 @@ def bench_ising64(args):
     cycles = 2.4e9 * kern_ms * 1e-3 / (L * L * S)
     # HBM bytes of one launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
     # of this kernel at this launch size (profiles/lattice_sweeps_ising64_hbm_counters.md)
-    traffic = HBM_BYTES_PER_LAUNCH if (S == 10000 and args.lanes_per_chain in (0, 16)) else None
+    traffic = HBM_BYTES_PER_LAUNCH if (S == 10000 and C == 4096 and args.lanes_per_chain in (0, 16)) else None
 
     out = {
         "metric": "spin-flip attempts/s (MUCA iteration, 1 GPU)",
@@ -316,7 +317,7 @@ def bench_ising64(args):
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "plain MUCA 2D Ising L=64 periodic, bit-packed spins, 4096 chains, "
+        "config": {"workload": f"plain MUCA 2D Ising L=64 periodic, bit-packed spins, {C} chains, "
                                f"seed 2, {S} sweeps per iteration, FP64 lnW, uint32 thresholds",
                    "L": L, "chains": C, "sweeps_per_iteration": S, "parallelism": "chains, 1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
