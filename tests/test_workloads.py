@@ -1,4 +1,6 @@
-"""Host-side workload definitions: sweeps from Eq. 4 and the seeded request stream."""
+"""Host-side workload definitions: sweeps from Eq. 4 and the seeded request stream;
+the benchmark's one-GPU contract."""
+import os
 import numpy as np
 
 from synth import WORKLOADS, m_opt, request_stream, sweeps_per_iteration
@@ -46,3 +48,15 @@ def test_served_requests_take_the_potts_law_for_q_at_least_3():
     assert r2.sweeps_per_iter == math.ceil(5.7 * 32 ** 2.51 / 256)
     ri = Request(id=2, arrival=0.0, model="ising", L=64, q=2, chains=2048, seed=1)
     assert ri.sweeps_per_iter == math.ceil(5.7 * 64 ** 2.51 / 2048)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with status 2 and
+    a message before any device work (runs on the CPU)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=root)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr and p.stdout == ""
