@@ -44,7 +44,7 @@ PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
 OPS_PER_ATTEMPT = 23.0
 # HBM bytes of one 10^4-sweep launch of the Ising L=64 kernel, from the
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a device copy of known size.
-HBM_BYTES_PER_LAUNCH = 3146.25 * 1024 * 2.0 + 2482.125 * 1024
+HBM_BYTES_PER_LAUNCH = 3141.875 * 1024 * 2.0 + 2482.125 * 1024
 
 
 def parse():

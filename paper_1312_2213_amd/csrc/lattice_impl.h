@@ -479,6 +479,49 @@ __device__ __forceinline__ void ising_lp_row(const uint32_t (&up)[Row1<L>::W], u
         const uint32_t w0 = window(s0, call), w1 = window(s1, call), wl = window(ML, call), wr = window(MR, call),
                        ws = window(cur, call);
         const bool last = call == (uint32_t)R::kCalls - 1u;
+        if constexpr (MODEL == kIsing) {
+            // Ising: the offset (-4n) and bin step (40 - 20n bytes) of a site
+            // depend only on its misalignment count n, so the four sites of
+            // the call are done bytewise (byte k = site k)
+            auto spread4 = [](uint32_t w) { return ((w & 0xFu) * 0x00204081u) & 0x01010101u; };
+            const uint32_t b0 = spread4(w0), b1 = spread4(w1), bl = spread4(wl);
+            const uint32_t cnt = b0 + (b1 << 1);
+            const uint32_t nA = cnt + bl;
+            // site 0's left neighbour (site L - 1) is not yet visited: no flip
+            const uint32_t nB = cnt + (bl ^ (call == 0u ? 0x01010100u : 0x01010101u));
+            // bytewise table lookups: byte n of {hi, lo} for the count n = 0..4
+            // of each site (offsets 0, -4, ..., -16; steps 40, 20, ..., -40)
+            const uint32_t OA = __builtin_amdgcn_perm(0x000000F0u, 0xF4F8FC00u, nA);
+            const uint32_t OB = __builtin_amdgcn_perm(0x000000F0u, 0xF4F8FC00u, nB);
+            const uint32_t SA = __builtin_amdgcn_perm(0x000000D8u, 0xEC001428u, nA);
+            const uint32_t SB = __builtin_amdgcn_perm(0x000000D8u, 0xEC001428u, nB);
+            // site 4 of the window (the next call's first site): its offsets
+            const uint32_t c4 = ((w1 >> 4) & 1u) * 2u + ((w0 >> 4) & 1u), l4 = (wl >> 4) & 1u;
+            const uint32_t E4 = last ? 0u : ((uint32_t)(-4 * (int32_t)(c4 + l4)) & 0xFFu) |
+                                                 (((uint32_t)(-4 * (int32_t)(c4 + (l4 ^ 1u))) & 0xFFu) << 8);
+            const uint32_t X0 = __builtin_amdgcn_perm(OB, OA, 0x06020501u);  // OA1 OB1 OA2 OB2
+            const uint32_t X3 = __builtin_amdgcn_perm(OB, OA, 0x0C0C0703u);  // OA3 OB3
+            const uint32_t X1 = __builtin_amdgcn_perm(E4, X3, 0x05040100u);  // OA3 OB3 OA4 OB4
+            const uint32_t Y0 = __builtin_amdgcn_perm(SB, SA, 0x05010400u);  // SA0 SB0 SA1 SB1
+            const uint32_t Y1 = __builtin_amdgcn_perm(SB, SA, 0x07030602u);  // SA2 SB2 SA3 SB3
+            const uint32_t D[4] = {__builtin_amdgcn_perm(Y0, X0, 0x05040100u), __builtin_amdgcn_perm(Y0, X0, 0x07060302u),
+                                   __builtin_amdgcn_perm(Y1, X1, 0x05040100u), __builtin_amdgcn_perm(Y1, X1, 0x07060302u)};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                pk[4 * m + k] = (uint64_t)D[k] | ((uint64_t)rng.w[4 * m + k] << 32);
+            if (m == 0)
+                first = __builtin_amdgcn_perm(OB, OA, 0x0C0C0400u); // OA0 OB0
+            if (m == (R::kCalls - 1) / LPC) {
+                // the row's last site (site 3 of the last call) with site 0 flipped
+                const uint32_t c3 = ((w1 >> 3) & 1u) * 2u + ((w0 >> 3) & 1u), l3 = (wl >> 3) & 1u;
+                const uint32_t c2 = ((wr >> 3) & 1u) ? c3 - 1u : c3 + 1u;
+                const uint32_t hoffv = ilp_off2<MODEL>(c2 + l3, c2 + (l3 ^ 1u), 0u);
+                const uint32_t hdsv = ilp_ds2<MODEL>(c2 + l3, c2 + (l3 ^ 1u), 0u);
+                dv2 = __builtin_amdgcn_perm(Y1, hoffv, 0x05040100u); // site L - 2: the last site's offsets
+                dv1 = hdsv << 16;                                     // site L - 1: its own bin steps
+            }
+            continue;
+        }
         // per site k of the window: both offsets (Hoff) and both bin steps (Hds)
         uint32_t hoff[5], hds[4], hoffv = 0u, hdsv = 0u;
 #pragma unroll
