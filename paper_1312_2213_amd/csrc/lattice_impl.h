@@ -479,26 +479,41 @@ __device__ __forceinline__ void ising_lp_row(const uint32_t (&up)[Row1<L>::W], u
         const uint32_t w0 = window(s0, call), w1 = window(s1, call), wl = window(ML, call), wr = window(MR, call),
                        ws = window(cur, call);
         const bool last = call == (uint32_t)R::kCalls - 1u;
-        if constexpr (MODEL == kIsing) {
-            // Ising: the offset (-4n) and bin step (40 - 20n bytes) of a site
-            // depend only on its misalignment count n, so the four sites of
-            // the call are done bytewise (byte k = site k)
+        if constexpr (MODEL == kIsing || MODEL == kMuma) {
+            // The offset and bin step of a site depend only on its
+            // misalignment count n = 0..4 (Ising: -4n and 40 - 20n bytes) or
+            // on n and its own spin (MUMA: 4 s - 8n and -40 / +40 for s = 1 /
+            // 0), so the four sites of the call are done bytewise (byte k =
+            // site k): table lookups by byte permutes, or byte arithmetic with
+            // a bias of 0x80 per byte so that no byte borrows
             auto spread4 = [](uint32_t w) { return ((w & 0xFu) * 0x00204081u) & 0x01010101u; };
             const uint32_t b0 = spread4(w0), b1 = spread4(w1), bl = spread4(wl);
             const uint32_t cnt = b0 + (b1 << 1);
             const uint32_t nA = cnt + bl;
             // site 0's left neighbour (site L - 1) is not yet visited: no flip
             const uint32_t nB = cnt + (bl ^ (call == 0u ? 0x01010100u : 0x01010101u));
-            // bytewise table lookups: byte n of {hi, lo} for the count n = 0..4
-            // of each site (offsets 0, -4, ..., -16; steps 40, 20, ..., -40)
-            const uint32_t OA = __builtin_amdgcn_perm(0x000000F0u, 0xF4F8FC00u, nA);
-            const uint32_t OB = __builtin_amdgcn_perm(0x000000F0u, 0xF4F8FC00u, nB);
-            const uint32_t SA = __builtin_amdgcn_perm(0x000000D8u, 0xEC001428u, nA);
-            const uint32_t SB = __builtin_amdgcn_perm(0x000000D8u, 0xEC001428u, nB);
+            uint32_t OA, OB, SA, SB;
+            if constexpr (MODEL == kIsing) {
+                // byte n of {hi, lo}: offsets 0, -4, ..., -16; steps 40, 20, ..., -40
+                OA = __builtin_amdgcn_perm(0x000000F0u, 0xF4F8FC00u, nA);
+                OB = __builtin_amdgcn_perm(0x000000F0u, 0xF4F8FC00u, nB);
+                SA = __builtin_amdgcn_perm(0x000000D8u, 0xEC001428u, nA);
+                SB = __builtin_amdgcn_perm(0x000000D8u, 0xEC001428u, nB);
+            } else {
+                const uint32_t bp = spread4(ws); // 1 in the bytes of +1 spins
+                const uint32_t base = (bp << 2) + 0x80808080u;
+                OA = (base - (nA << 3)) ^ 0x80808080u;
+                OB = (base - (nB << 3)) ^ 0x80808080u;
+                SA = SB = __builtin_amdgcn_perm(0u, 0x0000D828u, bp);
+            }
             // site 4 of the window (the next call's first site): its offsets
             const uint32_t c4 = ((w1 >> 4) & 1u) * 2u + ((w0 >> 4) & 1u), l4 = (wl >> 4) & 1u;
-            const uint32_t E4 = last ? 0u : ((uint32_t)(-4 * (int32_t)(c4 + l4)) & 0xFFu) |
-                                                 (((uint32_t)(-4 * (int32_t)(c4 + (l4 ^ 1u))) & 0xFFu) << 8);
+            uint32_t E4;
+            if constexpr (MODEL == kIsing)
+                E4 = last ? 0u : ((uint32_t)(-4 * (int32_t)(c4 + l4)) & 0xFFu) |
+                                     (((uint32_t)(-4 * (int32_t)(c4 + (l4 ^ 1u))) & 0xFFu) << 8);
+            else
+                E4 = last ? 0u : ilp_off2<MODEL>(c4 + l4, c4 + (l4 ^ 1u), (ws >> 4) & 1u);
             const uint32_t X0 = __builtin_amdgcn_perm(OB, OA, 0x06020501u);  // OA1 OB1 OA2 OB2
             const uint32_t X3 = __builtin_amdgcn_perm(OB, OA, 0x0C0C0703u);  // OA3 OB3
             const uint32_t X1 = __builtin_amdgcn_perm(E4, X3, 0x05040100u);  // OA3 OB3 OA4 OB4
@@ -515,8 +530,9 @@ __device__ __forceinline__ void ising_lp_row(const uint32_t (&up)[Row1<L>::W], u
                 // the row's last site (site 3 of the last call) with site 0 flipped
                 const uint32_t c3 = ((w1 >> 3) & 1u) * 2u + ((w0 >> 3) & 1u), l3 = (wl >> 3) & 1u;
                 const uint32_t c2 = ((wr >> 3) & 1u) ? c3 - 1u : c3 + 1u;
-                const uint32_t hoffv = ilp_off2<MODEL>(c2 + l3, c2 + (l3 ^ 1u), 0u);
-                const uint32_t hdsv = ilp_ds2<MODEL>(c2 + l3, c2 + (l3 ^ 1u), 0u);
+                const uint32_t p3 = MODEL == kIsing ? 0u : (ws >> 3) & 1u; // the Ising columns ignore the spin
+                const uint32_t hoffv = ilp_off2<MODEL>(c2 + l3, c2 + (l3 ^ 1u), p3);
+                const uint32_t hdsv = ilp_ds2<MODEL>(c2 + l3, c2 + (l3 ^ 1u), p3);
                 dv2 = __builtin_amdgcn_perm(Y1, hoffv, 0x05040100u); // site L - 2: the last site's offsets
                 dv1 = hdsv << 16;                                     // site L - 1: its own bin steps
             }
