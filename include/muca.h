@@ -144,21 +144,35 @@ int muca_workspace_bytes(const muca_config *cfg, uint64_t *bytes);
 int muca_init(const muca_config *cfg, void *d_workspace, uint64_t workspace_bytes,
               const float *h_positions, void *stream, muca_run **out);
 
-/* Enqueues `sweeps` sweeps of every chain with the current thresholds,
- * accumulating into the device histogram (asynchronous).  Repeated calls
- * before muca_merge_update extend the same iteration.  A sweep visits the
- * sites in row-major order (polymer: beads 0..N-1); after each sweep every
- * chain adds one entry to H.  Metropolis acceptance min(1, W(E')/W(E))
- * (MUMA: min(1, exp(-beta dE) W(M')/W(M))) by integer thresholds. */
+/* One iteration's sampling step (parallel-scheme paragraph and Fig. 1
+ * caption: every realisation runs M sweeps with the same weights W^(n) and
+ * fills its own histogram; Eq. 1 gives the multicanonical weight, Eq. 3 the
+ * multimagnetic one).  Enqueues `sweeps` (>= 1) sweeps of every chain with
+ * the current thresholds, accumulating into the device histogram; returns
+ * without waiting.  Repeated calls before muca_merge_update extend the same
+ * iteration (bit-identical to one call with the summed sweeps).  A sweep
+ * visits the sites in row-major order (polymer: beads 0..N-1); after each
+ * sweep every chain adds one entry to H.  Metropolis acceptance
+ * min(1, W(E')/W(E)) (MUMA: min(1, exp(-beta dE) W(M')/W(M))) by integer
+ * thresholds.  The chains, spins, bins and histogram stay in the run's
+ * device workspace.  MUCA_E_ARG for sweeps < 1 (run unchanged); MUCA_E_HIP
+ * if the launch fails (run poisoned). */
 int muca_run_iteration(muca_run *run, int64_t sweeps, void *stream);
 
 /* Same, but the sweeps are not histogrammed (thermalisation). */
 int muca_thermalize(muca_run *run, int64_t sweeps, void *stream);
 
-/* Ends iteration n: waits for the run's stream, merges H^(n), evaluates
- * flatness, applies the accumulated-statistics recursion in FP64 to obtain
- * lnW^(n+1), builds and uploads the new thresholds, clears H.  MUCA_E_STATE
- * if no sweeps were enqueued since the last merge. */
+/* Ends iteration n (parallel-scheme paragraph and Fig. 1 caption: the
+ * realisations' histograms are merged into H^(n), which decides flatness and
+ * gives the next weights W^(n+1) for all of them; the weights follow the
+ * accumulated-statistics recursion named in the paragraph after Eq. 2, which
+ * reduces to W^(n+1) = W^(n) / H^(n) on its first step).  Waits for the run's
+ * stream, reads the merged H^(n) (B x uint64, summed over all chains on the
+ * device), evaluates flatness (min / mean over the reachable bins), applies
+ * the recursion in FP64 to obtain lnW^(n+1), builds the new thresholds and
+ * enqueues their upload on the run's stream, and clears H.  `out` (may be
+ * NULL) receives the iteration's statistics.  MUCA_E_STATE if no sweeps were
+ * enqueued since the last merge; MUCA_E_HIP if a copy fails (run poisoned). */
 int muca_merge_update(muca_run *run, muca_iter_stats *out);
 
 /* Sharded runs (one run per device, each a consecutive range of the global

@@ -59,6 +59,36 @@ def test_batched_equals_plain(graph, lpc):
             assert np.array_equal(sa[2], sb[2]) and np.array_equal(sa[3], sb[3]), (it, k, "chains")
 
 
+def test_batched_equals_oracle():
+    """The mixed batch, element by element against the oracle: each run's
+    merged histogram, weights, thresholds, chain bins and spins after every
+    iteration of one persistent launch per round (lanes per chain chosen per
+    run, graph relaunches)."""
+    import torch
+    from oracle import oracle as orc
+    from paper_1312_2213_amd import muca
+    mid = {"ising": orc.ISING, "potts": orc.POTTS, "muma": orc.MUMA}
+    stream = torch.cuda.Stream()
+    batched = [make(s) for s in MIX]
+    oracle = [orc.LatticeRun(mid[m], L, c, seed, q=q, beta=0.5 if m == "muma" else 0.0)
+              for m, L, q, c, seed, _, _ in MIX]
+    batch = muca.Batch(len(MIX), lanes_per_chain=0, use_graph=True)
+    sweeps = [s[-1] for s in MIX]
+    for it in range(3):
+        print(f"  iteration {it}", flush=True)
+        with torch.cuda.stream(stream):
+            batch.run_iteration(batched, sweeps, stream=stream)
+        for k, (g, o, sw) in enumerate(zip(batched, oracle, sweeps)):
+            assert np.array_equal(g.thresholds(), o.thresholds()), (it, k, "thresholds")
+            H, f, _ = o.iterate(sw)
+            st = g.merge_update()
+            assert np.array_equal(g.last_hist(), H), (it, k, "histogram")
+            assert st["flatness"] == f, (it, k, "flatness")
+            assert np.all(np.abs(g.lnw() - o.lnW) <= 1e-12 * np.maximum(1.0, np.abs(o.lnW))), (it, k, "lnW")
+            s_, b_, _ = g.chain_state()
+            assert np.array_equal(s_, o.spins) and np.array_equal(b_, o.bins()), (it, k, "chains")
+
+
 def test_batched_subset_and_regrouping():
     """Runs can join and leave between rounds (the serving pattern)."""
     import torch

@@ -171,3 +171,38 @@ def test_move_set_is_refused_for_lattices():
     with pytest.raises(muca.MucaError):
         muca.Run(cfg)
 
+
+def divergent_chains(o, g):
+    """Chains whose bin or float positions differ from the oracle's, and the
+    largest relative difference of the running energies."""
+    pos, bins, E = g.chain_state()
+    bad = [c for c in range(o.n_chains) if bins[c] != o.bin[c] or not np.array_equal(pos[c], o.pos[c])]
+    rel = float(np.max(np.abs(E - o.E) / np.maximum(1.0, np.abs(o.E))))
+    return bad, rel
+
+
+@pytest.mark.parametrize("moves", [0, 1])
+def test_polymer_100_sweep_horizon(moves):
+    """100 sweeps in one launch (N = 40, 256 chains, sloped weights): the
+    device's FENE logarithm may differ from glibc's in the last bit, which
+    could move a running energy across a bin edge; every chain is compared
+    and the divergent ones counted (none expected: an ulp lands on an edge
+    with probability ~1e-13 per move).  moves = 1: the paper's parameters
+    and move set."""
+    print(f"polymer 100 sweeps moves={moves}", flush=True)
+    if moves:
+        o, g = pair_paper(40, 256, 77, lnw_slope=-1.5, moves=1)
+    else:
+        cent = -200.0 + 0.1 * (np.arange(2500) + 0.5)
+        o, g = pair(40, 256, 76, lnw=-0.7 * cent)
+    H = o.sweeps(100)
+    acc = o.take_accepted()
+    g.run_iteration(100)
+    st = g.merge_update()
+    bad, rel = divergent_chains(o, g)
+    print(f"  divergent chains: {len(bad)} of 256; running energies within {rel:.2e}; "
+          f"acceptance {st['accept_rate']:.3f}", flush=True)
+    assert not bad, bad[:8]
+    assert np.array_equal(g.last_hist(), H)
+    assert rel <= 1e-12
+    assert st["accept_rate"] > 0.05 and acc > 0

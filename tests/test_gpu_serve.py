@@ -1,8 +1,12 @@
 """Continuous batching: requests arriving while others run are admitted by
 footprint, share persistent launches, and each finishes with exactly the
-result it gets alone."""
+result it gets alone, which is the oracle's result for the same run (the
+method's iteration loop: sweeps, merged histogram, recursion, new weights;
+parallel-scheme paragraph and Fig. 1 caption)."""
 import numpy as np
 import pytest
+
+from oracle import oracle as orc
 
 pytestmark = pytest.mark.gpu
 
@@ -21,17 +25,34 @@ def reqs():
     return out
 
 
-def test_each_result_same_alone_and_in_the_mix():
+def oracle_run(req):
+    """The request's run (model, L, q, chains, seed, beta) in the oracle."""
+    model = {"ising": orc.ISING, "potts": orc.POTTS, "muma": orc.MUMA}[req.model]
+    beta = req.cfg.beta if req.cfg is not None and req.model == "muma" else 0.0
+    return orc.LatticeRun(model, req.L, req.chains, req.seed, q=req.q, beta=beta)
+
+
+def test_each_result_same_alone_in_the_mix_and_in_the_oracle():
     from paper_1312_2213_amd.serve import Server, run_alone
     srv = Server(hbm_budget=256 << 20, round_site_updates=4096, keep_results=True)
     mixed = srv.serve(reqs(), realtime=True)
     assert srv.rounds > len(mixed)  # chunked: several rounds per iteration
     assert srv.peak_active >= 2     # work of several requests overlapped on the device
     for r, req in zip(mixed, reqs()):
+        print(f"  request {req.id}: {req.model} L={req.L} q={req.q} chains={req.chains}", flush=True)
         alone = run_alone(req)
         assert r.iterations == alone.iterations and r.flat == alone.flat
         assert np.array_equal(r.hist, alone.hist), req
         assert np.array_equal(r.lnw, alone.lnw), req
+        o = oracle_run(req)
+        flats = [o.iterate(req.sweeps_per_iter) for _ in range(r.iterations)]
+        H = flats[-1][0]
+        f = [x[1] for x in flats]
+        # the request stopped at the oracle's first flat iteration (or its cap)
+        assert all(x <= req.flat_threshold for x in f[:-1]), (req, f)
+        assert (f[-1] > req.flat_threshold) == r.flat, (req, f)
+        assert np.array_equal(r.hist, H), req
+        assert np.all(np.abs(r.lnw - o.lnW) <= 1e-12 * np.maximum(1.0, np.abs(o.lnW))), req
 
 
 def test_admission_respects_the_memory_budget():

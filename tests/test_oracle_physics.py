@@ -102,21 +102,90 @@ def test_potts_q2_samples_ising_boltzmann(orc):
     assert np.abs(H[0::2][big] / H.sum() / p[big] - 1).max() < 0.06
 
 
-def test_config1_converges_to_exact_dos_and_canonical(orc):
-    """Ising L = 8, 16 chains, seed 1, 12 iterations of 2000 sweeps from
-    lnW = 0, then the final update: lnW^(12) + ln Omega is constant and the
-    reweighted u, c of the last iteration match the exact averages."""
+def _config1_per_chain(orc):
+    """Config 1 (Ising L = 8, 16 chains, seed 1, 12 iterations of 2000
+    sweeps from lnW = 0) with every chain's histogram of every iteration
+    kept.  Chains are independent (checked below), so running them one by
+    one with the iteration's table is the same run as iterate()."""
+    r = orc.LatticeRun(orc.ISING, 8, 16, seed=1, lo=-128, hi=128)
+    per, flats = [], []
+    for _ in range(12):
+        T = r.thresholds()
+        lnR_used = r.lnR.copy()
+        Hc = np.zeros((r.n_chains, r.n_bins), np.uint64)
+        for c in range(r.n_chains):
+            r.sweeps(2000, T, chains=(c, c + 1), H=Hc[c])
+        r.advance(2000)
+        lnw_used = r.lnW.copy()
+        H = Hc.sum(axis=0, dtype=np.uint64)
+        flats.append(r.merge_update(H))
+        per.append((lnR_used, lnw_used, Hc))
+    return r, per, flats
+
+
+def _pair_estimates(per, pairs, leave=None):
+    """Accumulated-statistics estimate of -(ln Omega(b) - ln Omega(a)) for
+    each pair (a, b) of consecutive reachable bins, written as the explicit
+    inverse-variance mean over iterations n of lnR_used^(n) + ln h_a - ln h_b
+    with weights h_a h_b / (h_a + h_b), optionally without chain `leave`."""
+    num = np.zeros(len(pairs))
+    den = np.zeros(len(pairs))
+    for lnR_used, _, Hc in per:
+        H = Hc.sum(axis=0).astype(float)
+        if leave is not None:
+            H = H - Hc[leave].astype(float)
+        for k, (a, b) in enumerate(pairs):
+            h0, h1 = H[a], H[b]
+            if h0 > 0 and h1 > 0:
+                p = h0 * h1 / (h0 + h1)
+                num[k] += p * (lnR_used[a] + math.log(h0) - math.log(h1))
+                den[k] += p
+    return num / den
+
+
+def test_config1_converges_to_exact_dos_within_jackknife_errors(orc):
+    """Config 1: lnW^(12) + ln Omega is constant within jackknife errors over
+    the 16 chains.  Tested on the increments between consecutive reachable
+    bins (the quantities the recursion estimates, nearly independent of each
+    other): leaving one chain out of every iteration's histogram gives 16
+    replicates of each increment and its jackknife error sigma; the exact
+    increment from the L = 8 density of states must lie within a few sigma
+    everywhere, and the z-scores must scatter like unit normals.  The same
+    statistic against the exact increments moved by one bin pair, with the
+    sign of ln Omega flipped, or off by 0.1 per pair, fails by far."""
     d8 = load("ising_dos_L8.txt")
     lnO = exact.ln_dos(d8)
-    r = orc.LatticeRun(orc.ISING, 8, 16, seed=1, lo=-128, hi=128)
-    flats = []
-    for _ in range(12):
-        H, f, lnw_used = r.iterate(2000)
-        flats.append(f)
+    r, per, flats = _config1_per_chain(orc)
     assert flats[0] == 0.0 and flats[-1] > 0.5
-    m = r.reachable() > 0
-    dev = (r.lnW + lnO)[m]
+    idx = np.flatnonzero(r.reachable() > 0)
+    pairs = list(zip(idx[:-1], idx[1:]))
+    full = _pair_estimates(per, pairs)
+    # the explicit mean is the oracle's recursion state
+    assert np.abs(full - r.lnR[idx[:-1]]).max() < 1e-12
+    C = r.n_chains
+    reps = np.array([_pair_estimates(per, pairs, k) for k in range(C)])
+    sig = np.sqrt((C - 1) / C * ((reps - reps.mean(axis=0)) ** 2).sum(axis=0))
+    assert np.all(sig > 0)
+    truth = np.array([lnO[a] - lnO[b] for a, b in pairs])
+    z = (full - truth) / sig
+    assert np.abs(z).max() < 4.5, z
+    assert 0.4 < np.mean(z ** 2) < 2.0, np.mean(z ** 2)
+    # lnW^(12) itself: the cumulative sum of those increments
+    dev = (r.lnW + lnO)[idx]
     assert np.ptp(dev) < 1.0
+    # plausible mistakes in the comparison are caught by the same statistic
+    for wrong in (np.roll(truth, 1), -truth, truth + 0.1):
+        zw = (full - wrong) / sig
+        assert np.abs(zw).max() > 6 or np.mean(zw ** 2) > 4
+
+
+def test_config1_reweighted_canonical_averages(orc):
+    """The reweighted u, c of config 1's last iteration (Eq. 2) match the
+    exact averages of the L = 8 density of states."""
+    d8 = load("ising_dos_L8.txt")
+    r, per, _ = _config1_per_chain(orc)
+    _, lnw_used, Hc = per[-1]
+    H = Hc.sum(axis=0, dtype=np.uint64)
     vals = [-128 + 4 * k for k in range(65)]
     for beta in (0.3, 0.44, 0.6):
         u, c = exact.canonical(d8, vals, beta, 64)
