@@ -276,6 +276,26 @@ int muca_batch_run_iteration(muca_batch *batch, muca_run *const *runs, int32_t n
                              void *stream);
 void muca_batch_free(muca_batch *batch);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * batched iteration of muca_batch_run_iteration without a batch handle or
+ * workspace.  Its work queue (counter, descriptors, work items) lives in a
+ * file-scope device array of the library, one per GPU, held until the
+ * process ends; the call allocates no device or pinned host memory.  Limits:
+ * at most MUCA_NOALLOC_MAX_RUNS runs and MUCA_NOALLOC_MAX_ITEMS work items
+ * (256 / lanes_per_chain chains each) per call, else MUCA_E_ARG with the run
+ * unchanged.  lanes_per_chain: 4, 16, or 0 to choose per run as
+ * muca_batch_create does.  The runs must live on the current device
+ * (MUCA_E_ARG otherwise).  No graph capture of this call; it returns after
+ * the launch has completed.  All calls on one GPU share that array: calls
+ * that overlap on one GPU (from several threads) race and are not allowed.
+ * Results are bit-identical to muca_batch_run_iteration and to plain
+ * launches.  Other errors as muca_batch_run_iteration. */
+#define MUCA_NOALLOC_MAX_RUNS 64
+#define MUCA_NOALLOC_MAX_ITEMS 4096
+int muca_batch_run_iteration_noalloc(muca_run *const *runs, int32_t n_runs, const int64_t *sweeps,
+                                     int32_t lanes_per_chain, void *stream);
+
 /* Autotuner: times `sweeps` sweeps of every compiled variant of cfg (layout,
  * lanes per chain, chains per block, threshold table in LDS or global) in
  * the caller's workspace d_ws and returns the fastest in *best (time per

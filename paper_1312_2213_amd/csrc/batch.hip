@@ -15,6 +15,7 @@
 // the pinned descriptor buffer (sweep counters and sweeps change per round).
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -244,30 +245,50 @@ static int l_index(int L)
     return -1;
 }
 
-static hipError_t enqueue_batch(muca_batch *b, int grid, size_t lds, hipStream_t s)
+// Where a round's header, descriptors and work items sit, for a staging area
+// sized for (max_runs, max_items): [header | descriptors | items].
+struct StageLayout {
+    size_t desc_off, items_off, bytes;
+};
+
+static StageLayout stage_layout(int max_runs, int max_items)
 {
-    hipError_t e = hipMemcpyAsync(b->d_hdr, b->h_buf, b->stage_bytes, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, b->d_counter);
-    e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(batch_persistent, dim3(grid), dim3(256), lds, s, b->d_hdr, b->d_counter, b->d_desc,
-                       b->d_items);
-    return hipGetLastError();
+    StageLayout l;
+    l.desc_off = a256(sizeof(BatchHeader));
+    l.items_off = l.desc_off + a256((size_t)max_runs * sizeof(BatchDesc));
+    l.bytes = l.items_off + a256((size_t)max_items * sizeof(BatchItem));
+    return l;
 }
 
-extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, int32_t n, const int64_t *sweeps,
-                                        void *stream)
-try {
-    if (!b || !runs || !sweeps || n < 1)
-        return muca_fail(MUCA_E_ARG, "bad arguments");
-    if (b->poisoned)
-        return muca_fail(MUCA_E_STATE, "batch poisoned by an earlier HIP error");
-    if (n > b->max_runs)
-        return muca_fail(MUCA_E_ARG, "%d runs exceed the batch capacity %d", n, b->max_runs);
-    hipStream_t s = (hipStream_t)stream;
+struct RoundPlan {
+    int grid = 0;
+    size_t lds = 0;
+    int n_items = 0;
+};
+
+// Plans one batched round: checks the runs, moves each to stream s, chooses
+// lanes per chain (lpc_fixed, or per run when 0), and writes the header, one
+// descriptor per run and the work items (longest first) into the host
+// staging area `stage`.  `lpc` and `order` are caller-owned work arrays of n
+// entries; nothing is allocated here, so the entry point that must not
+// allocate can use it.  Returns a muca_status.
+static int plan_round(muca_run *const *runs, int n, const int64_t *sweeps, int lpc_fixed, int max_runs, int max_items,
+                      int n_cus, int lds_limit, uint8_t *stage, int *lpc, int *order, hipStream_t s, RoundPlan *out)
+{
+    if (n > max_runs)
+        return muca_fail(MUCA_E_ARG, "%d runs exceed the batch capacity %d", n, max_runs);
+    for (int i = 0; i < n; ++i) {
+        muca_run *r = runs[i];
+        if (!r || r->poisoned)
+            return muca_fail(MUCA_E_STATE, "run %d is null or poisoned", i);
+        if (kind_of(r) < 0 || l_index(r->g.L) < 0)
+            return muca_fail(MUCA_E_ARG, "run %d (model %d, L %d) has no batched variant", i, r->g.model, r->g.L);
+        if (sweeps[i] < 1 || sweeps[i] > (int64_t)INT32_MAX)
+            return muca_fail(MUCA_E_ARG, "run %d: sweeps %lld out of range", i, (long long)sweeps[i]);
+        for (int k = 0; k < i; ++k)
+            if (runs[k] == r)
+                return muca_fail(MUCA_E_ARG, "run %d appears twice", i);
+    }
     // lanes per chain of each run.  Automatic choice: every run starts at 4;
     // runs are raised to 16 in order of decreasing per-chain work (the
     // critical path of the launch) while all lanes still fit one resident
@@ -275,61 +296,52 @@ try {
     // Work items cover the run's chains only: items made of padding chains
     // alone are not launched (padding chains are never histogrammed or read).
     auto items_of = [&](int i, int l) { return (long)((runs[i]->cfg.n_chains + 256 / l - 1) / (256 / l)); };
-    std::vector<int> lpc(n, b->lpc ? b->lpc : 4);
-    if (b->lpc == 0) {
-        std::vector<int> order(n);
+    auto work = [&](int i) {
+        return (runs[i]->g.model == kPotts ? 2.0 : 1.0) * (double)runs[i]->g.n_sites * (double)sweeps[i];
+    };
+    for (int i = 0; i < n; ++i)
+        lpc[i] = lpc_fixed ? lpc_fixed : 4;
+    if (lpc_fixed == 0) {
         long lanes = 0, n_items = 0;
         for (int i = 0; i < n; ++i) {
             order[i] = i;
-            if (runs[i]) {
-                lanes += items_of(i, 4) * 256;
-                n_items += items_of(i, 4);
-            }
+            lanes += items_of(i, 4) * 256;
+            n_items += items_of(i, 4);
         }
-        auto work = [&](int i) {
-            return (runs[i]->g.model == kPotts ? 2.0 : 1.0) * (double)runs[i]->g.n_sites * (double)sweeps[i];
-        };
-        for (int i = 0; i < n; ++i)
-            if (!runs[i])
-                return muca_fail(MUCA_E_STATE, "run %d is null", i);
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
-        const long cap = (long)b->n_cus * 256;
-        for (int i : order) {
+        std::sort(order, order + n, [&](int x, int y) {
+            const double wx = work(x), wy = work(y);
+            return wx != wy ? wx > wy : x < y;
+        });
+        const long cap = (long)n_cus * 256;
+        for (int k = 0; k < n; ++k) {
+            const int i = order[k];
             if (runs[i]->g.model == kPotts && runs[i]->g.L % 16)
                 continue; // Potts rows split over the lanes: 16 lanes need L a multiple of 16
             const long extra_items = items_of(i, 16) - items_of(i, 4), extra = extra_items * 256;
-            if (lanes + extra > cap || n_items + extra_items > b->max_items)
+            if (lanes + extra > cap || n_items + extra_items > max_items)
                 break;
             lanes += extra;
             n_items += extra_items;
             lpc[i] = 16;
         }
     }
-    struct Item {
-        double cost;
-        int inst, c_first;
-    };
-    std::vector<Item> items;
-    BatchHeader *hdr = (BatchHeader *)b->h_buf;
-    BatchDesc *desc = (BatchDesc *)(b->h_buf + a256(sizeof(BatchHeader)));
-    BatchItem *hitems = (BatchItem *)(b->h_buf + a256(sizeof(BatchHeader)) + a256((size_t)b->max_runs * sizeof(BatchDesc)));
+    long total_items = 0;
+    for (int i = 0; i < n; ++i)
+        total_items += items_of(i, lpc[i]);
+    if (total_items > max_items)
+        return muca_fail(MUCA_E_ARG, "%ld work items exceed the batch capacity %d", total_items, max_items);
+    const StageLayout sl = stage_layout(max_runs, max_items);
+    BatchHeader *hdr = (BatchHeader *)stage;
+    BatchDesc *desc = (BatchDesc *)(stage + sl.desc_off);
+    BatchItem *hitems = (BatchItem *)(stage + sl.items_off);
     size_t lds = 0;
-    const size_t lds_budget = (size_t)std::min(b->lds_limit, 160 * 1024) - 256; // static LDS of the kernel
+    const size_t lds_budget = (size_t)std::min(lds_limit, 160 * 1024) - 256; // static LDS of the kernel
+    int n_items = 0;
     for (int i = 0; i < n; ++i) {
         muca_run *r = runs[i];
-        if (!r || r->poisoned)
-            return muca_fail(MUCA_E_STATE, "run %d is null or poisoned", i);
         if (int rc = muca_use_stream(r, s))
             return rc; // the run's last threshold upload may still be queued elsewhere
-        const int kind = kind_of(r), li = l_index(r->g.L);
-        if (kind < 0 || li < 0)
-            return muca_fail(MUCA_E_ARG, "run %d (model %d, L %d) has no batched variant", i, r->g.model, r->g.L);
         const int cpi = 256 / lpc[i]; // chains per item
-        if (sweeps[i] < 1 || sweeps[i] > (int64_t)INT32_MAX)
-            return muca_fail(MUCA_E_ARG, "run %d: sweeps %lld out of range", i, (long long)sweeps[i]);
-        for (int k = 0; k < i; ++k)
-            if (runs[k] == r)
-                return muca_fail(MUCA_E_ARG, "run %d appears twice", i);
         const size_t hist = (size_t)lds_hist_words(r->g.n_bins) * 4u;
         const bool tlds = r->g.table_in_lds && r->g.lds_bytes <= lds_budget;
         lds = std::max(lds, tlds ? r->g.lds_bytes : hist);
@@ -351,27 +363,73 @@ try {
         d.a.table_in_lds = tlds ? 1 : 0;
         d.a.chain0 = r->cfg.chain0;
         d.a.accepts = r->d_hist + r->g.n_bins;
-        d.variant = variant_index(kind, li, tlds ? 1 : 0, lpc[i] == 16 ? 1 : 0);
-        const double per_site = r->g.model == kPotts ? 2.0 : 1.0;
-        const double cost = per_site * (double)r->g.n_sites * (double)sweeps[i];
+        d.variant = variant_index(kind_of(r), l_index(r->g.L), tlds ? 1 : 0, lpc[i] == 16 ? 1 : 0);
         for (int c0 = 0; c0 < r->cfg.n_chains; c0 += cpi)
-            items.push_back({cost, i, c0});
+            hitems[n_items++] = BatchItem{i, c0};
     }
-    if ((int)items.size() > b->max_items)
-        return muca_fail(MUCA_E_ARG, "%zu work items exceed the batch capacity %d", items.size(), b->max_items);
-    std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
+    // longest first (sites x sweeps x per-site cost); equal costs keep the
+    // run and chain order
+    std::sort(hitems, hitems + n_items, [&](const BatchItem &x, const BatchItem &y) {
+        const double cx = work(x.inst), cy = work(y.inst);
+        if (cx != cy)
+            return cx > cy;
+        return x.inst != y.inst ? x.inst < y.inst : x.c_first < y.c_first;
+    });
     std::memset(hdr, 0, sizeof *hdr);
-    hdr->n_items = (int32_t)items.size();
-    for (size_t k = 0; k < items.size(); ++k) {
-        hitems[k].inst = items[k].inst;
-        hitems[k].c_first = items[k].c_first;
-    }
+    hdr->n_items = n_items;
     // one resident workgroup per CU when the LDS staging is large, two otherwise
     const int per_cu = lds > 80u * 1024u ? 1 : 2;
-    const int grid = std::max(1, std::min((int)items.size(), b->n_cus * per_cu));
-    hipError_t e = hipSuccess;
+    out->grid = std::max(1, std::min(n_items, n_cus * per_cu));
+    out->lds = lds;
+    out->n_items = n_items;
+    return MUCA_OK;
+}
+
+static hipError_t set_lds(size_t lds)
+{
     if (lds > 65536u)
-        e = hipFuncSetAttribute((const void *)batch_persistent, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        return hipFuncSetAttribute((const void *)batch_persistent, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return hipSuccess;
+}
+
+static hipError_t enqueue_batch(muca_batch *b, int grid, size_t lds, hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(b->d_hdr, b->h_buf, b->stage_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, b->d_counter);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(batch_persistent, dim3(grid), dim3(256), lds, s, b->d_hdr, b->d_counter, b->d_desc,
+                       b->d_items);
+    return hipGetLastError();
+}
+
+static void advance_runs(muca_run *const *runs, int n, const int64_t *sweeps)
+{
+    for (int i = 0; i < n; ++i) {
+        runs[i]->sweep += (uint32_t)sweeps[i];
+        runs[i]->pending += sweeps[i];
+    }
+}
+
+extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, int32_t n, const int64_t *sweeps,
+                                        void *stream)
+try {
+    if (!b || !runs || !sweeps || n < 1)
+        return muca_fail(MUCA_E_ARG, "bad arguments");
+    if (b->poisoned)
+        return muca_fail(MUCA_E_STATE, "batch poisoned by an earlier HIP error");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int> lpc(n), order(n);
+    RoundPlan plan;
+    if (int rc = plan_round(runs, n, sweeps, b->lpc, b->max_runs, b->max_items, b->n_cus, b->lds_limit, b->h_buf,
+                            lpc.data(), order.data(), s, &plan))
+        return rc;
+    const int grid = plan.grid;
+    const size_t lds = plan.lds;
+    hipError_t e = set_lds(lds);
     if (e == hipSuccess && b->use_graph) {
         if (!b->exec || b->graph_stream != s || b->graph_grid != grid || b->graph_lds != lds) {
             drop_graph(b);
@@ -401,10 +459,117 @@ try {
             runs[i]->poisoned = true;
         return muca_fail(MUCA_E_HIP, "batched launch: %s", hipGetErrorString(e));
     }
-    for (int i = 0; i < n; ++i) {
-        runs[i]->sweep += (uint32_t)sweeps[i];
-        runs[i]->pending += sweeps[i];
+    advance_runs(runs, n, sweeps);
+    return MUCA_OK;
+}
+MUCA_ABI_CATCH
+
+// ---------------------------------------------------------------------------
+// The batched launch without a batch handle: its work queue lives in a
+// file-scope device array instead of a caller's workspace, for callers that
+// cannot allocate device memory.
+// ---------------------------------------------------------------------------
+namespace muca {
+constexpr int kScratchRuns = MUCA_NOALLOC_MAX_RUNS;
+constexpr int kScratchItems = MUCA_NOALLOC_MAX_ITEMS;
+constexpr size_t kScratchStage = 256 + // header
+                                 ((kScratchRuns * sizeof(BatchDesc) + 255) / 256) * 256 +
+                                 ((kScratchItems * sizeof(BatchItem) + 255) / 256) * 256;
+constexpr size_t kScratchBytes = 256 /* work counter */ + kScratchStage;
+constexpr int kMaxDevices = 64;
+} // namespace muca
+
+// [work counter | header | descriptors | items]; every GPU the library runs
+// on holds its own copy until the process ends.
+static __device__ __align__(256) uint8_t scratch[muca::kScratchBytes];
+
+static std::mutex g_scratch_mutex;
+static uint8_t *g_scratch[muca::kMaxDevices]; // device address of `scratch` per device
+
+// The device address of the current device's `scratch`, looked up once per
+// device (with that device current) on the first call there.
+static int scratch_address(uint8_t **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return muca_fail(MUCA_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= muca::kMaxDevices)
+        return muca_fail(MUCA_E_ARG, "device %d beyond the %d supported", dev, muca::kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return muca_fail(MUCA_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch[dev] = (uint8_t *)p;
     }
+    *out = g_scratch[dev];
+    return MUCA_OK;
+}
+
+extern "C" int muca_batch_run_iteration_noalloc(muca_run *const *runs, int32_t n, const int64_t *sweeps,
+                                                int32_t lanes_per_chain, void *stream)
+try {
+    if (!runs || !sweeps || n < 1)
+        return muca_fail(MUCA_E_ARG, "bad arguments");
+    if (n > kScratchRuns)
+        return muca_fail(MUCA_E_ARG, "%d runs exceed the no-allocation launch's maximum of %d", n, kScratchRuns);
+    if (lanes_per_chain != 0 && lanes_per_chain != 4 && lanes_per_chain != 16)
+        return muca_fail(MUCA_E_ARG, "batched launches use 4 or 16 lanes per chain (0: chosen per run)");
+    uint8_t *d_scratch = nullptr;
+    if (int rc = scratch_address(&d_scratch))
+        return rc;
+    int dev = 0, n_cus = 0, lds_limit = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&n_cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess)
+        return muca_fail(MUCA_E_HIP, "device attributes: %s", hipGetErrorString(e));
+    for (int i = 0; i < n; ++i) {
+        if (!runs[i])
+            return muca_fail(MUCA_E_STATE, "run %d is null", i);
+        hipPointerAttribute_t pa;
+        if (hipPointerGetAttributes(&pa, runs[i]->ws) != hipSuccess || pa.device != dev)
+            return muca_fail(MUCA_E_ARG, "run %d's workspace is not on the current device %d", i, dev);
+    }
+    // host staging on the stack: the copy below is complete before return
+    alignas(256) uint8_t stage[kScratchStage];
+    int lpc[kScratchRuns], order[kScratchRuns];
+    RoundPlan plan;
+    hipStream_t s = (hipStream_t)stream;
+    if (int rc = plan_round(runs, n, sweeps, lanes_per_chain, kScratchRuns, kScratchItems, n_cus, lds_limit, stage, lpc,
+                            order, s, &plan))
+        return rc;
+    const StageLayout sl = stage_layout(kScratchRuns, kScratchItems);
+    if (sl.bytes > kScratchStage)
+        return muca_fail(MUCA_E_STATE, "no-allocation staging of %zu bytes exceeds its array", sl.bytes);
+    int *d_counter = (int *)d_scratch;
+    uint8_t *d_stage = d_scratch + 256;
+    const size_t used = sl.items_off + (size_t)plan.n_items * sizeof(BatchItem);
+    e = set_lds(plan.lds);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_stage, stage, used, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, d_counter); // the queue starts at 0
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(batch_persistent, dim3(plan.grid), dim3(256), plan.lds, s, (const BatchHeader *)d_stage,
+                           d_counter, (const BatchDesc *)(d_stage + sl.desc_off),
+                           (const BatchItem *)(d_stage + sl.items_off));
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s); // the staging is on this stack frame; the next call rewrites `scratch`
+    if (e != hipSuccess) {
+        for (int i = 0; i < n; ++i)
+            runs[i]->poisoned = true;
+        return muca_fail(MUCA_E_HIP, "batched launch (no allocation): %s", hipGetErrorString(e));
+    }
+    advance_runs(runs, n, sweeps);
     return MUCA_OK;
 }
 MUCA_ABI_CATCH

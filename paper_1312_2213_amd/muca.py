@@ -80,6 +80,7 @@ def _load():
         "muca_batch_create": (ctypes.c_int, [i32, i32, i32, i32, vp, u64, P(vp)]),
         "muca_batch_run_iteration": (ctypes.c_int, [vp, P(vp), i32, P(ctypes.c_int64), vp]),
         "muca_batch_free": (None, [vp]),
+        "muca_batch_run_iteration_noalloc": (ctypes.c_int, [P(vp), i32, P(ctypes.c_int64), i32, vp]),
         "muca_autotune": (ctypes.c_int, [P(muca_config), vp, u64, i64, vp, P(muca_config), P(ctypes.c_double)]),
         "muca_sizes": (ctypes.c_int, [vp, P(i32), P(i32), P(i32)]),
         "muca_get_lnw": (ctypes.c_int, [vp, vp, i32]),
@@ -106,7 +107,8 @@ EXPORTED = ("muca_config_default", "muca_workspace_bytes", "muca_init", "muca_ru
             "muca_reweight", "muca_blocks_shape", "muca_run_iteration_blocks", "muca_reweight_jackknife",
             "muca_em_shape", "muca_run_iteration_em", "muca_reweight_em",
             "muca_batch_workspace_bytes",
-            "muca_batch_create", "muca_batch_run_iteration", "muca_batch_free", "muca_autotune", "muca_sizes", "muca_get_lnw", "muca_get_last_hist",
+            "muca_batch_create", "muca_batch_run_iteration", "muca_batch_free",
+            "muca_batch_run_iteration_noalloc", "muca_autotune", "muca_sizes", "muca_get_lnw", "muca_get_last_hist",
             "muca_get_thresholds", "muca_get_chain_state", "muca_set_lnw", "muca_set_thresholds",
             "muca_checkpoint", "muca_restore", "muca_free", "muca_last_error")
 
@@ -350,6 +352,18 @@ class Batch:
             self.free()
         except Exception:
             pass
+
+
+NOALLOC_MAX_RUNS, NOALLOC_MAX_ITEMS = 64, 4096
+
+
+def batch_run_iteration_noalloc(runs, sweeps, lanes_per_chain: int = 0, stream=None):
+    """One batched iteration of `runs` without a Batch (no workspace: the
+    work queue lives in the library's own device array)."""
+    n = len(runs)
+    handles = (ctypes.c_void_p * n)(*[r.handle.value for r in runs])
+    sw = (ctypes.c_int64 * n)(*[int(s) for s in (sweeps if np.ndim(sweeps) else [sweeps] * n)])
+    _check(LIB.muca_batch_run_iteration_noalloc(handles, n, sw, int(lanes_per_chain), _stream_handle(stream)))
 
 
 def muca_autotune(cfg: muca_config, sweeps: int, stream=None):
