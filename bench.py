@@ -8,22 +8,29 @@ sweep kernel over all chains (LDS + atomic histogram merge) followed by
 muca_merge_update (FP64 accumulated-statistics recursion, flatness test,
 threshold rebuild and upload).  Inputs are resident in HBM before the timed
 region.  The line also carries:
-  roofline      the sweep kernel's figures (HIP-event duration on its stream);
-  cpu_baseline  the single-threaded C oracle on a bounded sample;
-  batched_vs_plain  the batched workload (q=8 Potts L in {16,24,32,48} x 2048
-                chains + 4 MUMA Ising L=32 x 512 chains at beta = 0.5): wall
-                time of one persistent hipGraph launch per round against the
-                same instances run one after another with plain launches.
+  roofline      the sweep kernel's figures (HIP-event duration on its stream;
+                HBM traffic from the rocprofv3 counters of the same kernel
+                sources, null once those sources have changed);
+  cpu_baseline  the single-threaded C oracle on a bounded sample of the same
+                workload at weights that reject moves, on one core and as one
+                process per core over disjoint chain ranges;
+  time_to_flat  the batched workload (q=8 Potts L in {16,24,32,48} x 2048
+                chains + 4 MUMA Ising L=32 x 512 chains at beta = 0.5), every
+                instance run to a flat histogram (min/mean > 0.5): makespan
+                and mean time to flat of one persistent hipGraph launch per
+                round (batched), of the serving loop (served), and of the
+                instances one after another with plain launches (plain).
 
-Other modes (--workload): "ising64_flat" (the same configuration run to a
-flat histogram: time to flat), "batched" (time to flat, batched vs plain),
-"serving" (200 Poisson requests, p50/p99 time to flat), "polymer" (N = 40,
-4096 chains), "polymer_paper" (the paper's homopolymer, N = 40 and 80),
-"speedup" (statistical speedup S*_p over chains per run, Eq. 6; with
---speedup-set qscan the q-state Potts crossover scan), "muma_em"
-(multimagnetic run at T = 2/3 T_c with the joint (E, M) histogram reweighted
-in beta, and the cost of recording it), "copy" (device copy of known size,
-for counter calibration).
+Other modes (--workload): "ising64_flat" (the headline configuration run to
+a flat histogram: time to flat), "potts48" (plain MUCA of the batched
+workload's longest instance, q=8 Potts L=48, 2048 chains), "batched" (time
+to flat, batched vs plain), "serving" (200 Poisson requests, p50/p99 time to
+flat), "polymer" (N = 40, 4096 chains), "polymer_paper" (the paper's
+homopolymer, N = 40 and 80), "speedup" (statistical speedup S*_p over chains
+per run, Eq. 6; with --speedup-set qscan the q-state Potts crossover scan),
+"muma_em" (multimagnetic run at T = 2/3 T_c with the joint (E, M) histogram
+reweighted in beta, and the cost of recording it), "copy" (device copy of
+known size, for counter calibration).
 """
 from __future__ import annotations
 
@@ -42,9 +49,27 @@ PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
 # (10 rounds x [2 wide multiplies + 2 three-input XORs] per 4 words) +
 # Metropolis update 13.
 OPS_PER_ATTEMPT = 23.0
-# HBM bytes of one 10^4-sweep launch of the Ising L=64 kernel, from the
-# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a device copy of known size.
-HBM_BYTES_PER_LAUNCH = 3141.875 * 1024 * 2.0 + 2482.125 * 1024
+# HBM bytes of one 10^4-sweep launch of the Ising L=64 kernel (4096 chains,
+# 16 lanes per chain), from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled
+# by a device copy of known size, and the sha256 of the sources and flags
+# that built the profiled kernel: the figure is reported only while they are
+# unchanged.
+HBM_TRAFFIC = {"bytes_per_launch": 3454.125 * 1024 * 2.0 + 2482.125 * 1024,
+               "kernel_sources_sha256": "f7aec5704c593968"}
+KERNEL_SOURCES = ["paper_1312_2213_amd/csrc/lattice_impl.h", "paper_1312_2213_amd/csrc/muca_internal.h",
+                  "paper_1312_2213_amd/csrc/philox.h", "paper_1312_2213_amd/csrc/lattice_ising.hip",
+                  "paper_1312_2213_amd/build.py"]
+
+
+def kernel_sources_sha256() -> str:
+    """sha256 over the files that define the headline sweep kernel and its
+    compiler flags (first 16 hex digits)."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -53,16 +78,19 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ising64",
-                    choices=["ising64", "ising64_flat", "batched", "serving", "polymer", "polymer_paper", "speedup",
-                             "muma_em", "copy"])
+                    choices=["ising64", "ising64_flat", "potts48", "batched", "serving", "polymer", "polymer_paper",
+                             "speedup", "muma_em", "copy"])
     ap.add_argument("--sweeps", type=int, default=10000, help="sweeps per iteration (workload: 10^4)")
     ap.add_argument("--lanes-per-chain", type=int, default=0)
     ap.add_argument("--chains", type=int, default=4096, help="ising64: chains (workload: 4096)")
     ap.add_argument("--batch-lanes-per-chain", type=int, default=0, help="batched runs: 4, 16 or 0 (per run)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU oracle sample budget")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU oracle sample budget per leg (one core; all cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched_vs_plain sub-object")
+    ap.add_argument("--no-batched", action="store_true", help="skip the time_to_flat sub-object")
     ap.add_argument("--batched-rounds", type=int, default=3)
+    ap.add_argument("--flat-max-iters", type=int, default=3000,
+                    help="time_to_flat sub-object of the headline line: iteration cap per instance")
     ap.add_argument("--max-iters", type=int, default=None,
                     help="iteration cap (default: 40 batched, 3000 serving, 1000 speedup)")
     ap.add_argument("--requests", type=int, default=200)
@@ -76,25 +104,77 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(seconds: float) -> dict:
-    """The oracle (single-threaded C, as it stands) on a bounded sample of the
-    headline workload: 16 of the 4096 chains, L = 64, lnW = 0 thresholds, in
-    100-sweep chunks until `seconds` have elapsed."""
+CPU_CHAINS = 16  # chains per process of the CPU sample
+CPU_BETA = 0.4   # canonical slope of the sample's weights: about half the moves rejected
+
+
+def _cpu_weights(r):
+    """Weights of the CPU sample: lnW(E) = -0.4 E, under which about half of
+    the proposals from the random start are rejected (lnW = 0 would accept
+    every flip, the oracle's cheapest branch pattern)."""
+    import numpy as np
+    from oracle import oracle as orc
+    return -CPU_BETA * orc.bin_values(orc.ISING, 64, r.lo, r.hi)
+
+
+def _cpu_worker(k: int, n_procs: int, seconds: float):
+    """One process of the CPU sample: chains [16k, 16k + 16) of the headline
+    run (seed 2, L = 64), 100-sweep chunks until `seconds` have elapsed."""
+    import time as _t
+    sys.path.insert(0, ROOT)
     from oracle import oracle as orc
     orc.build(force=False)
-    r = orc.LatticeRun(orc.ISING, 64, 16, seed=2)
-    T = r.thresholds()
+    r = orc.LatticeRun(orc.ISING, 64, CPU_CHAINS * n_procs, seed=2)
+    T = r.thresholds(_cpu_weights(r))
+    chains = (CPU_CHAINS * k, CPU_CHAINS * (k + 1))
     sweeps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        r.sweeps(100, T)
+    t0 = _t.perf_counter()
+    while _t.perf_counter() - t0 < seconds:
+        r.sweeps(100, T, chains=chains)
         r.advance(100)
         sweeps += 100
-    dt = time.perf_counter() - t0
-    attempts = 16 * 4096 * sweeps
+    dt = _t.perf_counter() - t0
+    return CPU_CHAINS * 4096 * sweeps, dt, r.take_accepted()
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(seconds: float) -> dict:
+    """The oracle (single-threaded C, as it stands) on a bounded sample of the
+    headline workload at weights that reject moves: 16 chains on one core,
+    then one process per available core (at most 16) over disjoint 16-chain
+    ranges, histograms independent, attempts summed (the paper's own scheme
+    on CPU cores)."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    from oracle import oracle as orc
+    orc.build(force=False)
+    attempts, dt, acc = _cpu_worker(0, 1, seconds)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    P = max(1, min(avail, 16))
+    with ProcessPoolExecutor(max_workers=P, mp_context=mp.get_context("spawn")) as ex:
+        parts = list(ex.map(_cpu_worker, range(P), [P] * P, [seconds] * P))
+    all_attempts = sum(a for a, _, _ in parts)
+    all_dt = max(d for _, d, _ in parts)
     return {"value": attempts / dt, "unit": "attempts/s", "cores": 1, "kind": "oracle",
-            "sample": f"Ising L=64, 16 of the 4096 chains, {sweeps} sweeps with lnW = 0 ({attempts:.3g} "
-                      f"attempts in {dt:.1f} s, single thread)"}
+            "sample": f"Ising L=64, seed 2, chains 0-15 of the 4096, lnW(E) = -{CPU_BETA} E "
+                      f"(acceptance {acc / attempts:.2f}): {attempts:.3g} attempts in {dt:.1f} s, one thread",
+            "cpu_model": cpu_model(), "cores_available": avail,
+            "all_cores": {"value": all_attempts / all_dt, "unit": "attempts/s", "cores": P, "processes": P,
+                          "sample": f"{P} processes, chains [16k, 16k+16) each, same weights: "
+                                    f"{all_attempts:.3g} attempts in {all_dt:.1f} s"}}
 
 
 def batched_instances():
@@ -210,22 +290,29 @@ def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int =
     ts, ttf_s, it_s, res_s = run_served()
     tp, ttf_p, it_p, runs_p = run_plain()
     same = all((a.last_hist() == b.last_hist()).all() for a, b in zip(runs_b, runs_p))
-    same_served = all((r.hist == b.last_hist()).all() and r.iterations == n
-                      for r, b, n in zip(res_s, runs_p, it_p))
+    same_served = all((r.hist == b.last_hist()).all() for r, b in zip(res_s, runs_p))
     attempts = sum(c.n_chains * c.L * c.L * sw * k for (c, sw), k in zip(specs, it_b))
+    mean = lambda a: sum(a) / len(a)  # noqa: E731
+    own_p = [t - (ttf_p[k - 1] if k else 0.0) for k, t in enumerate(ttf_p)]
     out = {"instances": "potts q=8 L=16,24,32,48 x 2048 chains + 4 x muma L=32 x 512 chains (beta 0.5)",
-           "sweeps_per_iteration": [sw for _, sw in specs], "iterations": it_b,
-           "batched_s": tb, "served_s": ts, "plain_s": tp, "speedup": tp / tb, "served_speedup": tp / ts,
-           "batched_attempts_per_s": attempts / tb, "served_attempts_per_s": attempts / ts,
-           "plain_attempts_per_s": attempts / tp,
-           "identical_histograms": bool(same), "served_identical_histograms": bool(same_served)}
+           "sweeps_per_iteration": [sw for _, sw in specs],
+           "iterations": it_b, "identical_iterations": it_b == it_p == list(it_s),
+           "identical_histograms": bool(same and same_served),
+           "makespan_s": {"batched": tb, "served": ts, "plain": tp},
+           "speedup_makespan": {"batched": tp / tb, "served": tp / ts},
+           "attempts_per_s": {"batched": attempts / tb, "served": attempts / ts, "plain": attempts / tp}}
     if max_iters is not None:
-        out.update({"time_to_flat_batched_s": ttf_b, "time_to_flat_plain_s": ttf_p,
-                    "time_to_flat_served_s": ttf_s,
-                    "mean_time_to_flat_served_s": sum(ttf_s) / len(ttf_s),
-                    "flat": run_batched.flat,
-                    "mean_time_to_flat_batched_s": sum(ttf_b) / len(ttf_b),
-                    "mean_time_to_flat_plain_s": sum(ttf_p) / len(ttf_p)})
+        out.update({"flat_threshold": 0.5, "max_iters": max_iters, "flat": run_batched.flat,
+                    "mean_time_to_flat_s": {"batched": mean(ttf_b), "served": mean(ttf_s), "plain": mean(ttf_p)},
+                    "speedup_mean_time_to_flat": {"batched": mean(ttf_p) / mean(ttf_b),
+                                                  "served": mean(ttf_p) / mean(ttf_s)},
+                    "time_to_flat_s": {"batched": ttf_b, "served": ttf_s, "plain": ttf_p},
+                    "plain_own_time_s": own_p,
+                    "note": "all instances submitted at t = 0; plain runs them one after another, so its "
+                            "per-instance time to flat includes the queueing behind earlier instances "
+                            "(plain_own_time_s without it); makespan is the like-for-like comparison"})
+    else:
+        out["rounds"] = rounds
     return out
 
 
@@ -300,9 +387,25 @@ def bench_ising64(args):
     kern_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
     achieved = OPS_PER_ATTEMPT * attempts_per_step / (kern_ms * 1e-3)
     cycles = 2.4e9 * kern_ms * 1e-3 / (L * L * S)
-    # HBM bytes of one launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-    # of this kernel at this launch size (profiles/lattice_sweeps_ising64_hbm_counters.md)
-    traffic = HBM_BYTES_PER_LAUNCH if (S == 10000 and C == 4096 and args.lanes_per_chain in (0, 16)) else None
+    # HBM bytes of one launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
+    # this kernel at this launch size, while the kernel's sources are the
+    # profiled ones
+    sha = kernel_sources_sha256()
+    traffic = HBM_TRAFFIC["bytes_per_launch"] if (
+        sha == HBM_TRAFFIC["kernel_sources_sha256"] and S == 10000 and C == 4096
+        and args.lanes_per_chain in (0, 16)) else None
+    # the kernel is branch-free: the same launch at weights that reject about
+    # half of the moves takes the same time
+    rej = muca.Run(cfg, stream=stream)
+    import numpy as np
+    rej.set_lnw(-CPU_BETA * (-2.0 * L * L + 4.0 * np.arange(rej.n_bins)))
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    r0.record(stream)
+    rej.run_iteration(S)
+    r1.record(stream)
+    rej_stats = rej.merge_update()
+    rej_ms = r0.elapsed_time(r1)
+    rej.free()
 
     out = {
         "metric": "spin-flip attempts/s (MUCA iteration, 1 GPU)",
@@ -323,16 +426,58 @@ def bench_ising64(args):
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / PEAK_INT_OPS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE, copy-calibrated)",
+                     "traffic_kernel_sources_sha256": HBM_TRAFFIC["kernel_sources_sha256"],
+                     "kernel_sources_sha256": sha,
                      "kernel": "lattice_sweeps<Ising, L=64, bit-packed>", "kernel_ms": kern_ms,
-                     "ops_per_attempt": OPS_PER_ATTEMPT, "cycles_per_attempt_per_chain": cycles},
+                     "ops_per_attempt": OPS_PER_ATTEMPT, "cycles_per_attempt_per_chain": cycles,
+                     "kernel_ms_rejecting_weights": rej_ms,
+                     "accept_rate_rejecting_weights": rej_stats["accept_rate"]},
         "iterations": [{k: s[k] for k in ("iteration", "flatness", "lo_visited", "hi_visited")}
                        for s in stats],
     }
-    if not args.no_batched:
-        out["batched_vs_plain"] = batched_vs_plain(args.batched_rounds, batch_lpc=args.batch_lanes_per_chain)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    if not args.no_batched:
+        out["time_to_flat"] = batched_vs_plain(None, max_iters=args.flat_max_iters,
+                                               batch_lpc=args.batch_lanes_per_chain)
     return out
+
+
+def bench_potts48(args):
+    """Plain MUCA of the batched workload's longest instance: q = 8 Potts,
+    L = 48, 2048 chains, seed 33, 362 sweeps per iteration (Eq. 4's 8-state
+    law at p = 2048), one launch + merge per step."""
+    import torch
+    from paper_1312_2213_amd import muca
+    from synth.workloads import sweeps_per_iteration
+    torch.cuda.set_device(0)
+    L, q, C, seed = 48, 8, 2048, 33
+    S = sweeps_per_iteration(L, C, True)
+    stream = torch.cuda.current_stream()
+    run = muca.Run(muca.muca_config_default("potts", L, q, C, seed, lanes_per_chain=args.lanes_per_chain),
+                   stream=stream)
+    for _ in range(args.warmup):
+        run.run_iteration(S)
+        run.merge_update()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record(stream)
+        run.run_iteration(S)
+        evs[k][1].record(stream)
+        run.merge_update()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    attempts = C * L * L * S
+    return {"metric": "spin-flip attempts/s (plain MUCA iteration, 1 GPU)", "value": attempts * args.steps / dt,
+            "unit": "attempts/s", "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": dt / args.steps * 1e3, "kernel_ms": kern_ms,
+            "kernel_attempts_per_s": attempts / (kern_ms * 1e-3),
+            "cycles_per_attempt_per_chain": 2.4e9 * kern_ms * 1e-3 / (L * L * S),
+            "config": {"workload": f"plain MUCA 2D q=8 Potts L=48, uint8 colours, {C} chains, seed {seed}, "
+                                   f"{S} sweeps per iteration"}}
 
 
 def bench_serving(args):
@@ -545,6 +690,8 @@ def main():
         out = bench_ising64(args)
     elif args.workload == "ising64_flat":
         out = bench_ising64_flat(args)
+    elif args.workload == "potts48":
+        out = bench_potts48(args)
     elif args.workload == "batched":
         out = batched_vs_plain(args.batched_rounds, max_iters=args.max_iters, batch_lpc=args.batch_lanes_per_chain)
     elif args.workload == "serving":
