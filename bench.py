@@ -99,6 +99,9 @@ def parse():
                     help="speedup: the paper's spin systems, the q-state Potts crossover scan, or the "
                          "paper's homopolymer")
     ap.add_argument("--qscan-L", type=int, default=16, help="speedup --speedup-set qscan: lattice size")
+    ap.add_argument("--qscan-qs", default="", help="speedup --speedup-set qscan: comma-separated q values")
+    ap.add_argument("--qscan-ps", default="", help="speedup --speedup-set qscan: comma-separated chains per run")
+    ap.add_argument("--replicas", type=int, default=0, help="speedup --speedup-set qscan: runs per p")
     ap.add_argument("--round-site-updates", type=int, default=1 << 16,
                     help="serving: site updates per chain in one round")
     return ap.parse_args()
@@ -193,7 +196,41 @@ def batched_instances():
     return out
 
 
-def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int = 0) -> dict:
+def tuned_vs_rule_round(stream, rounds: int = 4) -> dict:
+    """One batched round of the batched workload's first iteration with the
+    lanes per chain and table placement chosen by the untuned rule and by the
+    measured item times (muca_batch_tune): minimum over `rounds` rounds of
+    each, on fresh runs of the same seeds, and the tuned choices."""
+    import torch
+    from paper_1312_2213_amd import muca
+    specs = batched_instances()
+    out = {}
+    for mode in ("rule", "tuned"):
+        runs = [muca.Run(c, stream=stream) for c, _ in specs]
+        batch = muca.Batch(len(runs), lanes_per_chain=0, use_graph=True, autotune=mode == "tuned")
+        best = None
+        for k in range(rounds + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            with torch.cuda.stream(stream):
+                batch.run_iteration(runs, [sw for _, sw in specs], stream=stream)
+            stream.synchronize()
+            dt = time.perf_counter() - t0
+            for r in runs:
+                r.merge_update()
+            if k:  # the first round loads the code (and tunes)
+                best = dt if best is None else min(best, dt)
+        out[f"{mode}_round_ms"] = best * 1e3
+        if mode == "tuned":
+            out["tuning"] = [r.batch_tuning for r in runs]
+        for r in runs:
+            r.free()
+        batch.free()
+    out["tuned_over_rule"] = out["tuned_round_ms"] / out["rule_round_ms"]
+    return out
+
+
+def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int = 0, autotune: bool = True) -> dict:
     """Same instances, same iterations: one batched graph launch per round vs
     plain launches one instance after another.  With max_iters, every
     instance runs until flat (or the cap) and time to flat is reported."""
@@ -231,7 +268,7 @@ def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int =
 
     def run_batched():
         runs = [muca.Run(c, stream=stream) for c, _ in specs]
-        batch = muca.Batch(len(runs), lanes_per_chain=batch_lpc, use_graph=True)
+        batch = muca.Batch(len(runs), lanes_per_chain=batch_lpc, use_graph=True, autotune=autotune)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         live = list(range(len(runs)))
@@ -278,7 +315,7 @@ def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int =
                 print(f"served: round {rounds}, {n_active} instances left", file=sys.stderr, flush=True)
 
         srv = Server(hbm_budget=1 << 40, chain_slots=1 << 20, lanes_per_chain=batch_lpc,
-                     keep_results=True, stream=stream, on_round=tick,
+                     keep_results=True, stream=stream, on_round=tick, autotune=autotune,
                      log=lambda r: print(f"served: instance {r.id} done after {r.iterations} iterations, "
                                          f"{r.finished:.1f} s", file=sys.stderr, flush=True))
         torch.cuda.synchronize()
@@ -286,6 +323,7 @@ def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int =
         res = srv.serve(reqs, realtime=False)
         return time.perf_counter() - t0, [r.time_to_flat for r in res], [r.iterations for r in res], res
 
+    tuned = tuned_vs_rule_round(stream) if autotune and batch_lpc == 0 else None
     tb, ttf_b, it_b, runs_b = run_batched()
     ts, ttf_s, it_s, res_s = run_served()
     tp, ttf_p, it_p, runs_p = run_plain()
@@ -300,7 +338,8 @@ def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int =
            "identical_histograms": bool(same and same_served),
            "makespan_s": {"batched": tb, "served": ts, "plain": tp},
            "speedup_makespan": {"batched": tp / tb, "served": tp / ts},
-           "attempts_per_s": {"batched": attempts / tb, "served": attempts / ts, "plain": attempts / tp}}
+           "attempts_per_s": {"batched": attempts / tb, "served": attempts / ts, "plain": attempts / tp},
+           "autotuned": bool(autotune and batch_lpc == 0), "tuned_vs_rule": tuned}
     if max_iters is not None:
         out.update({"flat_threshold": 0.5, "max_iters": max_iters, "flat": run_batched.flat,
                     "mean_time_to_flat_s": {"batched": mean(ttf_b), "served": mean(ttf_s), "plain": mean(ttf_p)},
@@ -648,7 +687,17 @@ def bench_speedup(args):
                               "seconds": res.seconds, "time": su.time_speedup(res), "flat": res.table("n_iter")}),
                   flush=True)
         return None
-    systems = su.paper_systems() if args.speedup_set == "paper" else su.q_scan_systems(args.qscan_L)
+    if args.speedup_set == "paper":
+        systems = su.paper_systems()
+    else:
+        kw = {}
+        if args.qscan_qs:
+            kw["qs"] = [int(x) for x in args.qscan_qs.split(",")]
+        if args.qscan_ps:
+            kw["ps"] = [int(x) for x in args.qscan_ps.split(",")]
+        if args.replicas:
+            kw["replicas"] = args.replicas
+        systems = su.q_scan_systems(args.qscan_L, **kw)
     if args.systems:
         systems = [systems[int(k)] for k in args.systems.split(",")]
     for system, ps, replicas in systems:
@@ -684,6 +733,10 @@ def main():
         print("bench.py measures one GPU only: this library has no multi-GPU path "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
         sys.exit(2)
+    if not os.environ.get("MUCA_AUTOTUNE_CACHE"):
+        # batched item times are measured once per class and reused by every leg
+        import tempfile
+        os.environ["MUCA_AUTOTUNE_CACHE"] = os.path.join(tempfile.gettempdir(), f"muca_autotune_{os.getpid()}.json")
     if args.max_iters is None:
         args.max_iters = {"serving": 3000, "speedup": 1000, "muma_em": 1000, "ising64_flat": 700}.get(args.workload, 40)
     if args.workload == "ising64":

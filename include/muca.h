@@ -175,6 +175,23 @@ int muca_thermalize(muca_run *run, int64_t sweeps, void *stream);
  * enqueued since the last merge; MUCA_E_HIP if a copy fails (run poisoned). */
 int muca_merge_update(muca_run *run, muca_iter_stats *out);
 
+/* muca_merge_update in two halves, so that the host part of a merge can
+ * overlap device work queued after it on the same stream (the serving loop
+ * launches the next batched round between them):
+ *   muca_merge_begin: enqueues the read-back of the merged histogram H^(n)
+ *     (and its clear) on the run's stream behind its sweeps and records an
+ *     event behind it; returns at once.  MUCA_E_STATE if no sweeps were
+ *     enqueued since the last merge.  Until muca_merge_finish, every other
+ *     call on the run except muca_free returns MUCA_E_STATE.
+ *   muca_merge_finish: waits for that event only (not for work queued on
+ *     the stream after muca_merge_begin), then flatness, recursion and the
+ *     new thresholds exactly as muca_merge_update, whose upload is enqueued
+ *     on the run's stream behind whatever is queued there.  MUCA_E_STATE
+ *     without a preceding muca_merge_begin.
+ * begin + finish with nothing in between is muca_merge_update. */
+int muca_merge_begin(muca_run *run);
+int muca_merge_finish(muca_run *run, muca_iter_stats *out);
+
 /* Sharded runs (one run per device, each a consecutive range of the global
  * chains, all with the same seed and weights; parallel-scheme paragraph:
  * the histograms of all realisations are merged and every part continues
@@ -256,18 +273,24 @@ int muca_reweight_em(const muca_run *run, const uint64_t *h_em, int64_t n_em, co
  * sweep code of muca_run_iteration, so every run's histogram and chains are
  * bit-identical to plain launches.
  *   muca_batch_workspace_bytes: device bytes for up to max_runs runs and
- *     max_items work items.
+ *     max_items work items (two staging areas, used by alternate rounds).
  *   muca_batch_create: lanes_per_chain 4 or 16 for every run, or 0 to
  *     choose per launch: runs start at 4 and, longest per-chain work first,
  *     move to 16 while all lanes fit one 256-thread workgroup per compute
- *     unit and the items fit max_items.  use_graph != 0 captures
- *     [descriptor upload, queue reset, persistent kernel] in a hipGraph once
- *     and relaunches it (requires a non-null stream).  d_ws is caller-owned
- *     (256-byte aligned); the handle owns a small pinned host buffer.
+ *     unit and the items fit max_items (see muca_batch_tune for runs whose
+ *     item times were measured).  use_graph != 0 captures [descriptor
+ *     upload, queue reset, persistent kernel] in a hipGraph once per staging
+ *     area and relaunches it (requires a non-null stream).  d_ws is
+ *     caller-owned (256-byte aligned); the handle owns two small pinned host
+ *     buffers.
  *   muca_batch_run_iteration: equivalent to muca_run_iteration(runs[i],
- *     sweeps[i]) for every i; returns after the launch has completed.
- *     MUCA_E_ARG for polymer runs, L outside {8,16,24,32,48,64}, a run given
- *     twice, or capacity exceeded. */
+ *     sweeps[i]) for every i; returns once the launch is enqueued.  Rounds
+ *     alternate between two staging areas, each fenced by an event, so the
+ *     next call can plan its round while this one runs (it waits only for
+ *     the round before this one).  MUCA_E_ARG for polymer runs, L outside
+ *     {8,16,24,32,48,64}, a run given twice, or capacity exceeded;
+ *     MUCA_E_STATE for a run whose merge was begun and not finished.
+ *     muca_batch_free waits for the rounds still reading its buffers. */
 typedef struct muca_batch muca_batch;
 int muca_batch_workspace_bytes(int32_t max_runs, int32_t max_items, uint64_t *bytes);
 int muca_batch_create(int32_t max_runs, int32_t max_items, int32_t lanes_per_chain, int32_t use_graph,
@@ -295,6 +318,40 @@ void muca_batch_free(muca_batch *batch);
 #define MUCA_NOALLOC_MAX_ITEMS 4096
 int muca_batch_run_iteration_noalloc(muca_run *const *runs, int32_t n_runs, const int64_t *sweeps,
                                      int32_t lanes_per_chain, void *stream);
+
+/* Autotuner of the batched launch (the batching pattern's chains per
+ * workgroup and table placement, per class of run).  Measures the time of
+ * one work item of the run's class (model, layout, L, q) for every candidate:
+ * 4 or 16 lanes per chain (64 or 16 chains per 256-thread work item), and
+ * the threshold table staged in LDS (where it fits) or read from global
+ * memory.  Each probe runs the run's first work item for probe_sweeps sweeps
+ * (0: about 5e4 site updates per chain) alone on the device; the run's
+ * device state is saved before and restored after, so its results do not
+ * change.  A candidate whose first 16 chains end in a different state than
+ * the first candidate's is rejected (counted in `rejected`).  Results are
+ * read from / written to the JSON file named by MUCA_AUTOTUNE_CACHE (key:
+ * architecture and class; an item's time does not depend on the number of
+ * chains).  The run keeps the measurement: a batched launch with
+ * lanes_per_chain 0 (muca_batch_create, muca_batch_run_iteration_noalloc)
+ * whose runs are all tuned takes per run the table placement of the faster
+ * item and the lanes per chain that minimise the estimated length of the
+ * round, max(longest item, total item time / compute units), starting from
+ * the choice of least total item time; items are ordered by their measured
+ * time.  The probes use the library's device array of
+ * muca_batch_run_iteration_noalloc: they must not overlap with such a call
+ * on the same GPU.  Returns after the probes have completed.  MUCA_E_ARG for
+ * a run without a batched variant; MUCA_E_HIP if a probe fails (run
+ * poisoned). */
+typedef struct muca_batch_tuning {
+    double us_per_sweep[2][2]; /* one item's time per sweep (microseconds):
+                                  [4 / 16 lanes per chain][table global / in LDS];
+                                  -1: not a candidate */
+    int32_t lanes_per_chain;   /* the candidate with the shortest item */
+    int32_t table_in_lds;
+    int32_t from_cache;        /* 1: read from MUCA_AUTOTUNE_CACHE */
+    int32_t rejected;          /* candidates that changed the chains */
+} muca_batch_tuning;
+int muca_batch_tune(muca_run *run, int64_t probe_sweeps, void *stream, muca_batch_tuning *out);
 
 /* Autotuner: times `sweeps` sweeps of every compiled variant of cfg (layout,
  * lanes per chain, chains per block, threshold table in LDS or global) in

@@ -43,8 +43,10 @@ std::string cache_key(const muca_config *c, const char *arch)
     return k.str();
 }
 
-// the cache is a flat JSON object {"key": [layout, lpc, chains_per_block, table_in_lds], ...}
-bool cache_lookup(const std::string &path, const std::string &key, int v[4])
+} // namespace
+
+// The cache is a flat JSON object {"key": [values], ...}, one entry per line.
+bool muca_cache_lookup(const std::string &path, const std::string &key, std::string &values)
 {
     std::ifstream f(path);
     if (!f)
@@ -56,10 +58,14 @@ bool cache_lookup(const std::string &path, const std::string &key, int v[4])
     const size_t p = s.find(pat);
     if (p == std::string::npos)
         return false;
-    return std::sscanf(s.c_str() + p + pat.size(), "%d, %d, %d, %d", &v[0], &v[1], &v[2], &v[3]) == 4;
+    const size_t e = s.find(']', p + pat.size());
+    if (e == std::string::npos)
+        return false;
+    values = s.substr(p + pat.size(), e - p - pat.size());
+    return true;
 }
 
-void cache_store(const std::string &path, const std::string &key, const int v[4])
+void muca_cache_store(const std::string &path, const std::string &key, const std::string &values)
 {
     std::string body;
     {
@@ -80,14 +86,27 @@ void cache_store(const std::string &path, const std::string &key, const int v[4]
             line.pop_back();
         lines.push_back(line);
     }
-    char buf[512];
-    std::snprintf(buf, sizeof buf, "  \"%s\": [%d, %d, %d, %d]", key.c_str(), v[0], v[1], v[2], v[3]);
-    lines.push_back(buf);
+    lines.push_back("  \"" + key + "\": [" + values + "]");
     std::ofstream o(path);
     o << "{\n";
     for (size_t i = 0; i < lines.size(); ++i)
         o << lines[i] << (i + 1 < lines.size() ? ",\n" : "\n");
     o << "}\n";
+}
+
+namespace {
+
+bool cache_lookup(const std::string &path, const std::string &key, int v[4])
+{
+    std::string t;
+    return muca_cache_lookup(path, key, t) && std::sscanf(t.c_str(), "%d, %d, %d, %d", &v[0], &v[1], &v[2], &v[3]) == 4;
+}
+
+void cache_store(const std::string &path, const std::string &key, const int v[4])
+{
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "%d, %d, %d, %d", v[0], v[1], v[2], v[3]);
+    muca_cache_store(path, key, buf);
 }
 
 } // namespace

@@ -14,8 +14,11 @@
 // kernel] once in a hipGraph and relaunches it every round after rewriting
 // the pinned descriptor buffer (sweep counters and sweeps change per round).
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -121,21 +124,31 @@ __global__ void batch_reset(int *counter) { *counter = 0; }
 
 using namespace muca;
 
-struct muca_batch {
-    int max_runs = 0, max_items = 0, lpc = 4;
-    bool use_graph = false;
-    uint8_t *d_ws = nullptr;
-    BatchHeader *d_hdr = nullptr;
+// One of the two staging areas of a batch handle: rounds alternate between
+// them, so a round's descriptors are written while the previous round may
+// still run; `done` is recorded behind the kernel that read the area.
+struct BatchSlot {
+    uint8_t *h_buf = nullptr; // pinned staging of header + descriptors + items
     int *d_counter = nullptr;
+    BatchHeader *d_hdr = nullptr;
     BatchDesc *d_desc = nullptr;
     BatchItem *d_items = nullptr;
-    uint8_t *h_buf = nullptr; // pinned staging of header + descriptors + items
-    size_t stage_bytes = 0;
+    hipEvent_t done = nullptr;
+    bool used = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t graph_stream = nullptr;
     int graph_grid = 0;
     size_t graph_lds = 0;
+};
+
+struct muca_batch {
+    int max_runs = 0, max_items = 0, lpc = 4;
+    bool use_graph = false;
+    uint8_t *d_ws = nullptr;
+    size_t stage_bytes = 0;
+    BatchSlot slot[2];
+    int next = 0;
     int n_cus = 0, lds_limit = 0;
     bool poisoned = false;
 };
@@ -148,14 +161,53 @@ static size_t stage_size(int max_runs, int max_items)
            a256((size_t)max_items * sizeof(BatchItem));
 }
 
+// Where a round's header, descriptors and work items sit, for a staging area
+// sized for (max_runs, max_items): [header | descriptors | items].
+struct StageLayout {
+    size_t desc_off, items_off, bytes;
+};
+
+static StageLayout stage_layout(int max_runs, int max_items)
+{
+    StageLayout l;
+    l.desc_off = a256(sizeof(BatchHeader));
+    l.items_off = l.desc_off + a256((size_t)max_runs * sizeof(BatchDesc));
+    l.bytes = l.items_off + a256((size_t)max_items * sizeof(BatchItem));
+    return l;
+}
+
 extern "C" int muca_batch_workspace_bytes(int32_t max_runs, int32_t max_items, uint64_t *bytes)
 try {
     if (max_runs < 1 || max_items < 1 || !bytes)
         return muca_fail(MUCA_E_ARG, "bad arguments");
-    *bytes = 256 + stage_size(max_runs, max_items);
+    *bytes = 2 * (256 + stage_size(max_runs, max_items)); // two staging areas
     return MUCA_OK;
 }
 MUCA_ABI_CATCH
+
+static void drop_graph(BatchSlot &sl)
+{
+    if (sl.exec)
+        (void)hipGraphExecDestroy(sl.exec);
+    if (sl.graph)
+        (void)hipGraphDestroy(sl.graph);
+    sl.exec = nullptr;
+    sl.graph = nullptr;
+}
+
+static void release(muca_batch *b)
+{
+    for (BatchSlot &sl : b->slot) {
+        if (sl.used && sl.done)
+            (void)hipEventSynchronize(sl.done); // the pinned staging may still be read
+        drop_graph(sl);
+        if (sl.done)
+            (void)hipEventDestroy(sl.done);
+        if (sl.h_buf)
+            (void)hipHostFree(sl.h_buf);
+    }
+    delete b;
+}
 
 extern "C" int muca_batch_create(int32_t max_runs, int32_t max_items, int32_t lanes_per_chain, int32_t use_graph,
                                  void *d_ws, uint64_t ws_bytes, muca_batch **out)
@@ -180,13 +232,20 @@ try {
     b->lpc = lanes_per_chain;
     b->use_graph = use_graph != 0;
     b->d_ws = (uint8_t *)d_ws;
-    b->d_counter = (int *)b->d_ws;
-    uint8_t *p = b->d_ws + 256;
-    b->d_hdr = (BatchHeader *)p;
-    b->d_desc = (BatchDesc *)(p + a256(sizeof(BatchHeader)));
-    b->d_items = (BatchItem *)(p + a256(sizeof(BatchHeader)) + a256((size_t)max_runs * sizeof(BatchDesc)));
     b->stage_bytes = stage_size(max_runs, max_items);
-    hipError_t e = hipHostMalloc((void **)&b->h_buf, b->stage_bytes, hipHostMallocDefault);
+    const StageLayout sl = stage_layout(max_runs, max_items);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        BatchSlot &t = b->slot[k];
+        uint8_t *p = b->d_ws + (size_t)k * (256 + b->stage_bytes);
+        t.d_counter = (int *)p;
+        t.d_hdr = (BatchHeader *)(p + 256);
+        t.d_desc = (BatchDesc *)(p + 256 + sl.desc_off);
+        t.d_items = (BatchItem *)(p + 256 + sl.items_off);
+        e = hipHostMalloc((void **)&t.h_buf, b->stage_bytes, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&t.done, hipEventDisableTiming);
+    }
     int dev = 0;
     if (e == hipSuccess)
         e = hipGetDevice(&dev);
@@ -195,9 +254,7 @@ try {
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&b->lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) {
-        if (b->h_buf)
-            (void)hipHostFree(b->h_buf);
-        delete b;
+        release(b);
         return muca_fail(MUCA_E_HIP, "batch create: %s", hipGetErrorString(e));
     }
     *out = b;
@@ -205,24 +262,10 @@ try {
 }
 MUCA_ABI_CATCH
 
-static void drop_graph(muca_batch *b)
-{
-    if (b->exec)
-        (void)hipGraphExecDestroy(b->exec);
-    if (b->graph)
-        (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
-}
-
 extern "C" void muca_batch_free(muca_batch *b)
 {
-    if (!b)
-        return;
-    drop_graph(b);
-    if (b->h_buf)
-        (void)hipHostFree(b->h_buf);
-    delete b;
+    if (b)
+        release(b);
 }
 
 static int kind_of(const muca_run *r)
@@ -245,35 +288,117 @@ static int l_index(int L)
     return -1;
 }
 
-// Where a round's header, descriptors and work items sit, for a staging area
-// sized for (max_runs, max_items): [header | descriptors | items].
-struct StageLayout {
-    size_t desc_off, items_off, bytes;
-};
-
-static StageLayout stage_layout(int max_runs, int max_items)
-{
-    StageLayout l;
-    l.desc_off = a256(sizeof(BatchHeader));
-    l.items_off = l.desc_off + a256((size_t)max_runs * sizeof(BatchDesc));
-    l.bytes = l.items_off + a256((size_t)max_items * sizeof(BatchItem));
-    return l;
-}
-
 struct RoundPlan {
     int grid = 0;
     size_t lds = 0;
     int n_items = 0;
 };
 
+// The descriptor of run r for `sweeps` sweeps from its current sweep counter.
+static void fill_desc(BatchDesc &d, const muca_run *r, int64_t sweeps, bool tlds, int lpc)
+{
+    std::memset(&d, 0, sizeof d);
+    d.a.words = r->d_words;
+    d.a.bins = r->d_bins;
+    d.a.thresholds = r->d_table;
+    d.a.hist = r->d_hist;
+    d.a.k0 = (uint32_t)(r->cfg.seed & 0xffffffffu);
+    d.a.k1 = (uint32_t)(r->cfg.seed >> 32);
+    d.a.g0 = r->sweep;
+    d.a.n_sweeps = (int32_t)sweeps;
+    d.a.n_chains = r->cfg.n_chains;
+    d.a.c_pad = r->g.c_pad;
+    d.a.n_bins = r->g.n_bins;
+    d.a.q = r->cfg.q;
+    d.a.record = 1;
+    d.a.table_in_lds = tlds ? 1 : 0;
+    d.a.chain0 = r->cfg.chain0;
+    d.a.accepts = r->d_hist + r->g.n_bins;
+    d.variant = variant_index(kind_of(r), l_index(r->g.L), tlds ? 1 : 0, lpc == 16 ? 1 : 0);
+}
+
+// Lanes per chain, table placement and item cost of every run of a round,
+// from the runs' measured item times (muca_batch_tune).  The chip is taken
+// as n_cus slots, each running one work item at a time, and the round's
+// length is estimated as max(longest item, total item time / slots): every
+// run starts at the choice of least total item time, then the run with the
+// longest item moves to the choice with the shorter item while that lowers
+// the estimate.  Returns false if some run is not tuned.
+static bool plan_tuned(muca_run *const *runs, int n, const int64_t *sweeps, int n_cus, int max_items, int *lpc,
+                       int *tlds, double *cost)
+{
+    for (int i = 0; i < n; ++i)
+        if (!runs[i]->batch_tuned)
+            return false;
+    auto items_of = [&](int i, int o) { return (double)((runs[i]->cfg.n_chains + 256 / (o ? 16 : 4) - 1) /
+                                                        (256 / (o ? 16 : 4))); };
+    // per-item time of option o (0: 4 lanes, 1: 16 lanes) at the faster table placement
+    auto item_t = [&](int i, int o, int *tl) {
+        const double g = runs[i]->batch_us[o][0], l = runs[i]->batch_us[o][1];
+        double best = -1.0;
+        int t = 0;
+        if (g >= 0.0)
+            best = g, t = 0;
+        if (l >= 0.0 && (best < 0.0 || l < best))
+            best = l, t = 1;
+        if (tl)
+            *tl = t;
+        return best < 0.0 ? -1.0 : best * (double)sweeps[i];
+    };
+    double total = 0.0, items = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double w4 = item_t(i, 0, nullptr), w16 = item_t(i, 1, nullptr);
+        int o = 0;
+        if (w4 < 0.0 || (w16 >= 0.0 && items_of(i, 1) * w16 < items_of(i, 0) * w4))
+            o = 1;
+        if (item_t(i, o, nullptr) < 0.0)
+            return false;
+        lpc[i] = o ? 16 : 4;
+        total += items_of(i, o) * item_t(i, o, nullptr);
+        items += items_of(i, o);
+    }
+    auto estimate = [&](double tot) {
+        double longest = 0.0;
+        for (int i = 0; i < n; ++i)
+            longest = std::max(longest, item_t(i, lpc[i] == 16, nullptr));
+        return std::max(longest, tot / (double)n_cus);
+    };
+    double est = estimate(total);
+    for (int step = 0; step < n; ++step) {
+        int k = 0;
+        for (int i = 1; i < n; ++i)
+            if (item_t(i, lpc[i] == 16, nullptr) > item_t(k, lpc[k] == 16, nullptr))
+                k = i;
+        const int o = lpc[k] == 16, alt = 1 - o;
+        const double now = item_t(k, o, nullptr), other = item_t(k, alt, nullptr);
+        if (other < 0.0 || other >= now)
+            break;
+        const double tot2 = total - items_of(k, o) * now + items_of(k, alt) * other;
+        const double items2 = items - items_of(k, o) + items_of(k, alt);
+        lpc[k] = alt ? 16 : 4;
+        const double est2 = estimate(tot2);
+        if (est2 >= est || items2 > (double)max_items) {
+            lpc[k] = o ? 16 : 4;
+            break;
+        }
+        est = est2, total = tot2, items = items2;
+    }
+    for (int i = 0; i < n; ++i)
+        cost[i] = item_t(i, lpc[i] == 16, &tlds[i]);
+    return true;
+}
+
 // Plans one batched round: checks the runs, moves each to stream s, chooses
-// lanes per chain (lpc_fixed, or per run when 0), and writes the header, one
-// descriptor per run and the work items (longest first) into the host
-// staging area `stage`.  `lpc` and `order` are caller-owned work arrays of n
-// entries; nothing is allocated here, so the entry point that must not
-// allocate can use it.  Returns a muca_status.
+// lanes per chain (lpc_fixed, or per run when 0: from the measured item
+// times when every run is tuned, else by the rule below) and the table
+// placement, and writes the header, one descriptor per run and the work
+// items (longest first) into the host staging area `stage`.  `lpc`, `tlds`,
+// `order` and `cost` are caller-owned work arrays of n entries; nothing is
+// allocated here, so the entry point that must not allocate can use it.
+// Returns a muca_status.
 static int plan_round(muca_run *const *runs, int n, const int64_t *sweeps, int lpc_fixed, int max_runs, int max_items,
-                      int n_cus, int lds_limit, uint8_t *stage, int *lpc, int *order, hipStream_t s, RoundPlan *out)
+                      int n_cus, int lds_limit, uint8_t *stage, int *lpc, int *tlds, int *order, double *cost,
+                      hipStream_t s, RoundPlan *out)
 {
     if (n > max_runs)
         return muca_fail(MUCA_E_ARG, "%d runs exceed the batch capacity %d", n, max_runs);
@@ -281,6 +406,8 @@ static int plan_round(muca_run *const *runs, int n, const int64_t *sweeps, int l
         muca_run *r = runs[i];
         if (!r || r->poisoned)
             return muca_fail(MUCA_E_STATE, "run %d is null or poisoned", i);
+        if (r->merge_begun)
+            return muca_fail(MUCA_E_STATE, "run %d: a merge was begun and not finished", i);
         if (kind_of(r) < 0 || l_index(r->g.L) < 0)
             return muca_fail(MUCA_E_ARG, "run %d (model %d, L %d) has no batched variant", i, r->g.model, r->g.L);
         if (sweeps[i] < 1 || sweeps[i] > (int64_t)INT32_MAX)
@@ -289,19 +416,25 @@ static int plan_round(muca_run *const *runs, int n, const int64_t *sweeps, int l
             if (runs[k] == r)
                 return muca_fail(MUCA_E_ARG, "run %d appears twice", i);
     }
-    // lanes per chain of each run.  Automatic choice: every run starts at 4;
-    // runs are raised to 16 in order of decreasing per-chain work (the
-    // critical path of the launch) while all lanes still fit one resident
-    // 256-thread workgroup per CU and the item list its capacity.
-    // Work items cover the run's chains only: items made of padding chains
-    // alone are not launched (padding chains are never histogrammed or read).
+    const size_t lds_budget = (size_t)std::min(lds_limit, 160 * 1024) - 256; // static LDS of the kernel
     auto items_of = [&](int i, int l) { return (long)((runs[i]->cfg.n_chains + 256 / l - 1) / (256 / l)); };
+    // untuned rule: the per-site cost of Potts counted twice that of Ising
     auto work = [&](int i) {
         return (runs[i]->g.model == kPotts ? 2.0 : 1.0) * (double)runs[i]->g.n_sites * (double)sweeps[i];
     };
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         lpc[i] = lpc_fixed ? lpc_fixed : 4;
-    if (lpc_fixed == 0) {
+        tlds[i] = runs[i]->g.table_in_lds && runs[i]->g.lds_bytes <= lds_budget;
+        cost[i] = work(i);
+    }
+    if (lpc_fixed == 0 && plan_tuned(runs, n, sweeps, n_cus, max_items, lpc, tlds, cost)) {
+        for (int i = 0; i < n; ++i) // a measured LDS placement must still fit this device
+            tlds[i] = tlds[i] && runs[i]->g.table_in_lds && runs[i]->g.lds_bytes <= lds_budget;
+    } else if (lpc_fixed == 0) {
+        // every run starts at 4 lanes per chain; runs are raised to 16 in
+        // order of decreasing per-chain work (the critical path of the
+        // launch) while all lanes still fit one resident 256-thread
+        // workgroup per CU and the item list its capacity
         long lanes = 0, n_items = 0;
         for (int i = 0; i < n; ++i) {
             order[i] = i;
@@ -325,6 +458,8 @@ static int plan_round(muca_run *const *runs, int n, const int64_t *sweeps, int l
             lpc[i] = 16;
         }
     }
+    // Work items cover the run's chains only: items made of padding chains
+    // alone are not launched (padding chains are never histogrammed or read).
     long total_items = 0;
     for (int i = 0; i < n; ++i)
         total_items += items_of(i, lpc[i]);
@@ -335,7 +470,6 @@ static int plan_round(muca_run *const *runs, int n, const int64_t *sweeps, int l
     BatchDesc *desc = (BatchDesc *)(stage + sl.desc_off);
     BatchItem *hitems = (BatchItem *)(stage + sl.items_off);
     size_t lds = 0;
-    const size_t lds_budget = (size_t)std::min(lds_limit, 160 * 1024) - 256; // static LDS of the kernel
     int n_items = 0;
     for (int i = 0; i < n; ++i) {
         muca_run *r = runs[i];
@@ -343,34 +477,14 @@ static int plan_round(muca_run *const *runs, int n, const int64_t *sweeps, int l
             return rc; // the run's last threshold upload may still be queued elsewhere
         const int cpi = 256 / lpc[i]; // chains per item
         const size_t hist = (size_t)lds_hist_words(r->g.n_bins) * 4u;
-        const bool tlds = r->g.table_in_lds && r->g.lds_bytes <= lds_budget;
-        lds = std::max(lds, tlds ? r->g.lds_bytes : hist);
-        BatchDesc &d = desc[i];
-        std::memset(&d, 0, sizeof d);
-        d.a.words = r->d_words;
-        d.a.bins = r->d_bins;
-        d.a.thresholds = r->d_table;
-        d.a.hist = r->d_hist;
-        d.a.k0 = (uint32_t)(r->cfg.seed & 0xffffffffu);
-        d.a.k1 = (uint32_t)(r->cfg.seed >> 32);
-        d.a.g0 = r->sweep;
-        d.a.n_sweeps = (int32_t)sweeps[i];
-        d.a.n_chains = r->cfg.n_chains;
-        d.a.c_pad = r->g.c_pad;
-        d.a.n_bins = r->g.n_bins;
-        d.a.q = r->cfg.q;
-        d.a.record = 1;
-        d.a.table_in_lds = tlds ? 1 : 0;
-        d.a.chain0 = r->cfg.chain0;
-        d.a.accepts = r->d_hist + r->g.n_bins;
-        d.variant = variant_index(kind_of(r), l_index(r->g.L), tlds ? 1 : 0, lpc[i] == 16 ? 1 : 0);
+        lds = std::max(lds, tlds[i] ? r->g.lds_bytes : hist);
+        fill_desc(desc[i], r, sweeps[i], tlds[i] != 0, lpc[i]);
         for (int c0 = 0; c0 < r->cfg.n_chains; c0 += cpi)
             hitems[n_items++] = BatchItem{i, c0};
     }
-    // longest first (sites x sweeps x per-site cost); equal costs keep the
-    // run and chain order
+    // longest first (per-item cost); equal costs keep the run and chain order
     std::sort(hitems, hitems + n_items, [&](const BatchItem &x, const BatchItem &y) {
-        const double cx = work(x.inst), cy = work(y.inst);
+        const double cx = cost[x.inst], cy = cost[y.inst];
         if (cx != cy)
             return cx > cy;
         return x.inst != y.inst ? x.inst < y.inst : x.c_first < y.c_first;
@@ -392,17 +506,17 @@ static hipError_t set_lds(size_t lds)
     return hipSuccess;
 }
 
-static hipError_t enqueue_batch(muca_batch *b, int grid, size_t lds, hipStream_t s)
+static hipError_t enqueue_batch(muca_batch *b, const BatchSlot &sl, int grid, size_t lds, hipStream_t s)
 {
-    hipError_t e = hipMemcpyAsync(b->d_hdr, b->h_buf, b->stage_bytes, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(sl.d_hdr, sl.h_buf, b->stage_bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, b->d_counter);
+    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, sl.d_counter);
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(batch_persistent, dim3(grid), dim3(256), lds, s, b->d_hdr, b->d_counter, b->d_desc,
-                       b->d_items);
+    hipLaunchKernelGGL(batch_persistent, dim3(grid), dim3(256), lds, s, sl.d_hdr, sl.d_counter, sl.d_desc,
+                       sl.d_items);
     return hipGetLastError();
 }
 
@@ -422,43 +536,53 @@ try {
     if (b->poisoned)
         return muca_fail(MUCA_E_STATE, "batch poisoned by an earlier HIP error");
     hipStream_t s = (hipStream_t)stream;
-    std::vector<int> lpc(n), order(n);
+    BatchSlot &sl = b->slot[b->next];
+    // this staging area was last read by the round before the previous one
+    hipError_t e = sl.used ? hipEventSynchronize(sl.done) : hipSuccess;
+    if (e != hipSuccess) {
+        b->poisoned = true;
+        return muca_fail(MUCA_E_HIP, "batched launch: %s", hipGetErrorString(e));
+    }
+    std::vector<int> lpc(n), tlds(n), order(n);
+    std::vector<double> cost(n);
     RoundPlan plan;
-    if (int rc = plan_round(runs, n, sweeps, b->lpc, b->max_runs, b->max_items, b->n_cus, b->lds_limit, b->h_buf,
-                            lpc.data(), order.data(), s, &plan))
+    if (int rc = plan_round(runs, n, sweeps, b->lpc, b->max_runs, b->max_items, b->n_cus, b->lds_limit, sl.h_buf,
+                            lpc.data(), tlds.data(), order.data(), cost.data(), s, &plan))
         return rc;
     const int grid = plan.grid;
     const size_t lds = plan.lds;
-    hipError_t e = set_lds(lds);
+    e = set_lds(lds);
     if (e == hipSuccess && b->use_graph) {
-        if (!b->exec || b->graph_stream != s || b->graph_grid != grid || b->graph_lds != lds) {
-            drop_graph(b);
+        if (!sl.exec || sl.graph_stream != s || sl.graph_grid != grid || sl.graph_lds != lds) {
+            drop_graph(sl);
             e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                hipError_t e2 = enqueue_batch(b, grid, lds, s);
-                e = hipStreamEndCapture(s, &b->graph);
+                hipError_t e2 = enqueue_batch(b, sl, grid, lds, s);
+                e = hipStreamEndCapture(s, &sl.graph);
                 if (e == hipSuccess)
                     e = e2;
             }
             if (e == hipSuccess)
-                e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-            b->graph_stream = s;
-            b->graph_grid = grid;
-            b->graph_lds = lds;
+                e = hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0);
+            sl.graph_stream = s;
+            sl.graph_grid = grid;
+            sl.graph_lds = lds;
         }
         if (e == hipSuccess)
-            e = hipGraphLaunch(b->exec, s);
+            e = hipGraphLaunch(sl.exec, s);
     } else if (e == hipSuccess) {
-        e = enqueue_batch(b, grid, lds, s);
+        e = enqueue_batch(b, sl, grid, lds, s);
     }
     if (e == hipSuccess)
-        e = hipStreamSynchronize(s); // the pinned descriptors are rewritten by the next call
+        e = hipEventRecord(sl.done, s);
     if (e != hipSuccess) {
         b->poisoned = true;
         for (int i = 0; i < n; ++i)
             runs[i]->poisoned = true;
         return muca_fail(MUCA_E_HIP, "batched launch: %s", hipGetErrorString(e));
     }
+    sl.used = true;
+    b->next ^= 1;
     advance_runs(runs, n, sweeps);
     return MUCA_OK;
 }
@@ -537,11 +661,12 @@ try {
     }
     // host staging on the stack: the copy below is complete before return
     alignas(256) uint8_t stage[kScratchStage];
-    int lpc[kScratchRuns], order[kScratchRuns];
+    int lpc[kScratchRuns], tlds[kScratchRuns], order[kScratchRuns];
+    double cost[kScratchRuns];
     RoundPlan plan;
     hipStream_t s = (hipStream_t)stream;
     if (int rc = plan_round(runs, n, sweeps, lanes_per_chain, kScratchRuns, kScratchItems, n_cus, lds_limit, stage, lpc,
-                            order, s, &plan))
+                            tlds, order, cost, s, &plan))
         return rc;
     const StageLayout sl = stage_layout(kScratchRuns, kScratchItems);
     if (sl.bytes > kScratchStage)
@@ -570,6 +695,182 @@ try {
         return muca_fail(MUCA_E_HIP, "batched launch (no allocation): %s", hipGetErrorString(e));
     }
     advance_runs(runs, n, sweeps);
+    return MUCA_OK;
+}
+MUCA_ABI_CATCH
+
+// ---------------------------------------------------------------------------
+// Autotuner of the batched launch: the time of one work item of a run's
+// class (model, layout, L, q) for every candidate (4 or 16 lanes per chain,
+// threshold table in LDS or in global memory), measured on probe launches of
+// the run's first work item that are undone afterwards.
+// ---------------------------------------------------------------------------
+static std::string batch_cache_key(const muca_run *r, const char *arch)
+{
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "batch/%s/m%d/lay%d/L%d/q%d", arch, r->g.model, r->g.layout, r->g.L, r->cfg.q);
+    return buf;
+}
+
+// One work item (the run's chains [0, 256 / lpc)) of `sweeps` sweeps alone
+// on the device, timed by events around the kernel.
+static hipError_t probe_item(muca_run *r, uint8_t *d_scratch, int lpc, bool tlds, int64_t sweeps, hipStream_t s,
+                             hipEvent_t e0, hipEvent_t e1, float *ms)
+{
+    const StageLayout sl = stage_layout(1, 1);
+    alignas(256) uint8_t stage[768];
+    static_assert(sizeof(BatchDesc) <= 256 && sizeof(BatchItem) <= 256, "probe staging layout");
+    std::memset(stage, 0, sizeof stage);
+    ((BatchHeader *)stage)->n_items = 1;
+    fill_desc(*(BatchDesc *)(stage + sl.desc_off), r, sweeps, tlds, lpc);
+    *(BatchItem *)(stage + sl.items_off) = BatchItem{0, 0};
+    const size_t lds = tlds ? r->g.lds_bytes : (size_t)lds_hist_words(r->g.n_bins) * 4u;
+    uint8_t *d_stage = d_scratch + 256;
+    hipError_t e = set_lds(lds);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_stage, stage, sl.bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, (int *)d_scratch);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipEventRecord(e0, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(batch_persistent, dim3(1), dim3(256), lds, s, (const BatchHeader *)d_stage,
+                           (int *)d_scratch, (const BatchDesc *)(d_stage + sl.desc_off),
+                           (const BatchItem *)(d_stage + sl.items_off));
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipEventRecord(e1, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s); // the staging is on this stack frame
+    if (e == hipSuccess && ms)
+        e = hipEventElapsedTime(ms, e0, e1);
+    return e;
+}
+
+static uint64_t fnv1a64(uint64_t h, const void *p, size_t n)
+{
+    const uint8_t *b = (const uint8_t *)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+extern "C" int muca_batch_tune(muca_run *r, int64_t probe_sweeps, void *stream, muca_batch_tuning *out)
+try {
+    if (!r || r->poisoned)
+        return muca_fail(MUCA_E_STATE, "null or poisoned run");
+    if (r->merge_begun)
+        return muca_fail(MUCA_E_STATE, "a merge was begun and not finished");
+    if (kind_of(r) < 0 || l_index(r->g.L) < 0)
+        return muca_fail(MUCA_E_ARG, "model %d, L %d has no batched variant", r->g.model, r->g.L);
+    if (probe_sweeps < 0 || probe_sweeps > (int64_t)INT32_MAX)
+        return muca_fail(MUCA_E_ARG, "probe sweeps %lld out of range", (long long)probe_sweeps);
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0, lds_limit = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return muca_fail(MUCA_E_HIP, "no device");
+    muca_batch_tuning t;
+    std::memset(&t, 0, sizeof t);
+    for (auto &row : t.us_per_sweep)
+        row[0] = row[1] = -1.0;
+    const char *env = std::getenv("MUCA_AUTOTUNE_CACHE");
+    const std::string key = batch_cache_key(r, prop.gcnArchName);
+    std::string cached;
+    if (env && *env && muca_cache_lookup(env, key, cached) &&
+        std::sscanf(cached.c_str(), "%lf, %lf, %lf, %lf", &t.us_per_sweep[0][0], &t.us_per_sweep[0][1],
+                    &t.us_per_sweep[1][0], &t.us_per_sweep[1][1]) == 4) {
+        t.from_cache = 1;
+    } else {
+        if (int rc = muca_use_stream(r, s))
+            return rc;
+        uint8_t *d_scratch = nullptr;
+        if (int rc = scratch_address(&d_scratch))
+            return rc;
+        const int64_t sw = probe_sweeps ? probe_sweeps : std::max<int64_t>(1, (50000 + r->g.n_sites - 1) / r->g.n_sites);
+        const size_t lds_budget = (size_t)std::min(lds_limit, 160 * 1024) - 256;
+        const bool lds_fits = r->g.table_in_lds && r->g.lds_bytes <= lds_budget;
+        // the probes change the run's device state (the first item's chains,
+        // bins, histogram, accepted-move count): saved here, restored after each
+        std::vector<uint8_t> saved(r->g.ws_bytes);
+        HIP_OR_POISON(r, hipStreamSynchronize(s));
+        HIP_OR_POISON(r, hipMemcpy(saved.data(), r->ws, saved.size(), hipMemcpyDeviceToHost));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess)
+            e = hipEventCreate(&e1);
+        const int nc = std::min(16, r->cfg.n_chains);
+        std::vector<uint8_t> state((size_t)nc * r->g.n_sites);
+        std::vector<int32_t> bins(nc);
+        bool have_ref = false;
+        uint64_t ref = 0;
+        if (e == hipSuccess) // loads the code and warms the caches: untimed
+            e = probe_item(r, d_scratch, 16, lds_fits, sw, s, e0, e1, nullptr);
+        for (int o = 0; o < 2 && e == hipSuccess; ++o)
+            for (int tl = 1; tl >= 0 && e == hipSuccess; --tl) {
+                if (tl && !lds_fits)
+                    continue;
+                e = hipMemcpy(r->ws, saved.data(), saved.size(), hipMemcpyHostToDevice);
+                float ms = 0.0f;
+                if (e == hipSuccess)
+                    e = probe_item(r, d_scratch, o ? 16 : 4, tl != 0, sw, s, e0, e1, &ms);
+                if (e != hipSuccess)
+                    break;
+                if (int rc = muca_get_chain_state(r, 0, nc, state.data(), bins.data(), nullptr)) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    return rc;
+                }
+                uint64_t h = fnv1a64(1469598103934665603ull, state.data(), state.size());
+                h = fnv1a64(h, bins.data(), bins.size() * 4);
+                if (!have_ref) {
+                    ref = h;
+                    have_ref = true;
+                } else if (h != ref) {
+                    ++t.rejected;
+                    std::fprintf(stderr, "muca_batch_tune: %d lanes per chain, table %s changed the chains; "
+                                         "rejected\n", o ? 16 : 4, tl ? "in LDS" : "global");
+                    continue;
+                }
+                t.us_per_sweep[o][tl] = (double)ms * 1e3 / (double)sw;
+            }
+        if (e == hipSuccess)
+            e = hipMemcpy(r->ws, saved.data(), saved.size(), hipMemcpyHostToDevice);
+        if (e0)
+            (void)hipEventDestroy(e0);
+        if (e1)
+            (void)hipEventDestroy(e1);
+        if (e != hipSuccess) {
+            r->poisoned = true;
+            return muca_fail(MUCA_E_HIP, "batch tuning: %s", hipGetErrorString(e));
+        }
+        if (env && *env && t.rejected == 0) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "%.6g, %.6g, %.6g, %.6g", t.us_per_sweep[0][0], t.us_per_sweep[0][1],
+                          t.us_per_sweep[1][0], t.us_per_sweep[1][1]);
+            muca_cache_store(env, key, buf);
+        }
+    }
+    double best = -1.0;
+    for (int o = 0; o < 2; ++o)
+        for (int tl = 0; tl < 2; ++tl)
+            if (t.us_per_sweep[o][tl] >= 0.0 && (best < 0.0 || t.us_per_sweep[o][tl] < best)) {
+                best = t.us_per_sweep[o][tl];
+                t.lanes_per_chain = o ? 16 : 4;
+                t.table_in_lds = tl;
+            }
+    if (best < 0.0)
+        return muca_fail(MUCA_E_STATE, "no batched candidate kept its results");
+    std::memcpy(r->batch_us, t.us_per_sweep, sizeof r->batch_us);
+    r->batch_tuned = true;
+    if (out)
+        *out = t;
     return MUCA_OK;
 }
 MUCA_ABI_CATCH

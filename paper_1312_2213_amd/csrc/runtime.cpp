@@ -42,15 +42,6 @@ int muca_fail(int code, const char *fmt, ...)
 
 const char *muca_last_error(void) { return g_last_error; }
 
-#define HIP_OR_POISON(run, expr)                                                                   \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) {                                                                    \
-            (run)->poisoned = true;                                                                \
-            return muca_fail(MUCA_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));                  \
-        }                                                                                          \
-    } while (0)
-
 static size_t align256(size_t x) { return (x + 255u) & ~(size_t)255u; }
 
 // ---------------------------------------------------------------------------
@@ -412,11 +403,15 @@ static int check_run(const muca_run *r)
         return muca_fail(MUCA_E_ARG, "null run");
     if (r->poisoned)
         return muca_fail(MUCA_E_STATE, "run poisoned by an earlier HIP error");
+    if (r->merge_begun)
+        return muca_fail(MUCA_E_STATE, "a merge was begun and not finished (muca_merge_finish)");
     return MUCA_OK;
 }
 
 muca_run::~muca_run()
 {
+    if (merge_ev)
+        (void)hipEventDestroy(merge_ev);
     if (h_hist)
         (void)hipHostFree(h_hist);
 }
@@ -747,23 +742,46 @@ int muca_finish_iteration(muca_run *r, const uint64_t *H, uint64_t accepted, muc
     r->have_last = true;
     if (st)
         *st = s;
-    return muca_rebuild_thresholds(r); // every merge path synchronised the stream
+    // every merge path has waited for the work queued before the read-back,
+    // the last upload from the pinned threshold mirror included
+    return muca_rebuild_thresholds(r);
 }
 
-extern "C" int muca_merge_update(muca_run *r, muca_iter_stats *st)
+extern "C" int muca_merge_begin(muca_run *r)
 try {
     int rc = check_run(r);
     if (rc)
         return rc;
     if (r->pending <= 0)
-        return muca_fail(MUCA_E_STATE, "merge_update without sweeps since the last merge");
-    const int B = r->g.n_bins;
+        return muca_fail(MUCA_E_STATE, "merge without sweeps since the last merge");
     if (r->h_hist) {
         // the histogram and the accepted-move count behind it are written to
         // pinned host memory and cleared by one kernel queued behind the
-        // sweeps: one dispatch and one wait per merge
-        HIP_OR_POISON(r, launch_drain_u64(r->d_hist, r->h_hist_dev, B + 1, r->stream));
-        HIP_OR_POISON(r, hipStreamSynchronize(r->stream));
+        // sweeps; the event behind it is all that muca_merge_finish waits for
+        if (!r->merge_ev)
+            HIP_OR_POISON(r, hipEventCreateWithFlags(&r->merge_ev, hipEventDisableTiming));
+        HIP_OR_POISON(r, launch_drain_u64(r->d_hist, r->h_hist_dev, r->g.n_bins + 1, r->stream));
+        HIP_OR_POISON(r, hipEventRecord(r->merge_ev, r->stream));
+    }
+    r->merge_begun = true;
+    return MUCA_OK;
+}
+MUCA_ABI_CATCH
+
+extern "C" int muca_merge_finish(muca_run *r, muca_iter_stats *st)
+try {
+    if (!r)
+        return muca_fail(MUCA_E_ARG, "null run");
+    if (r->poisoned)
+        return muca_fail(MUCA_E_STATE, "run poisoned by an earlier HIP error");
+    if (!r->merge_begun)
+        return muca_fail(MUCA_E_STATE, "muca_merge_finish without muca_merge_begin");
+    r->merge_begun = false;
+    const int B = r->g.n_bins;
+    if (r->h_hist) {
+        // the read-back is behind the sweeps and behind the last threshold
+        // upload, so the pinned mirror may be rewritten once it has completed
+        HIP_OR_POISON(r, hipEventSynchronize(r->merge_ev));
         return muca_finish_iteration(r, r->h_hist, r->h_hist[B], st);
     }
     std::vector<uint64_t> H(B + 1); // the histogram and the accepted-move count behind it
@@ -771,6 +789,13 @@ try {
     HIP_OR_POISON(r, hipMemcpy(H.data(), r->d_hist, (size_t)(B + 1) * 8u, hipMemcpyDeviceToHost));
     HIP_OR_POISON(r, launch_fill_u64(r->d_hist, B + 1, r->stream));
     return muca_finish_iteration(r, H.data(), H[B], st);
+}
+MUCA_ABI_CATCH
+
+extern "C" int muca_merge_update(muca_run *r, muca_iter_stats *st)
+try {
+    int rc = muca_merge_begin(r);
+    return rc ? rc : muca_merge_finish(r, st);
 }
 MUCA_ABI_CATCH
 

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/muca.h"
@@ -77,10 +78,34 @@ struct muca_run {
     // count read back at a merge, and its device-side address
     uint64_t *h_hist = nullptr;
     unsigned long long *h_hist_dev = nullptr;
+    // measured time of one batched work item per sweep (microseconds), by
+    // [4 / 16 lanes per chain][table in global memory / in LDS]; < 0: not
+    // measured or not a candidate (muca_batch_tune)
+    double batch_us[2][2] = {{-1.0, -1.0}, {-1.0, -1.0}};
+    bool batch_tuned = false;
+    // a merge split into muca_merge_begin / muca_merge_finish: the event
+    // recorded behind the histogram read-back, and whether one is under way
+    hipEvent_t merge_ev = nullptr;
+    bool merge_begun = false;
     ~muca_run();
 };
 
 int muca_fail(int code, const char *fmt, ...);
+
+// A HIP call whose failure poisons the run and returns MUCA_E_HIP.
+#define HIP_OR_POISON(run, expr)                                                                   \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) {                                                                    \
+            (run)->poisoned = true;                                                                \
+            return muca_fail(MUCA_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));                  \
+        }                                                                                          \
+    } while (0)
+
+// The autotuners' JSON cache (MUCA_AUTOTUNE_CACHE): `values` is the text
+// between the brackets of the entry `key`.
+bool muca_cache_lookup(const std::string &path, const std::string &key, std::string &values);
+void muca_cache_store(const std::string &path, const std::string &key, const std::string &values);
 
 // Handlers of a C entry point's function-try-block: no exception crosses the
 // ABI (host allocations are the only source: std::bad_alloc).

@@ -44,6 +44,17 @@ class muca_config(ctypes.Structure):
                 ("moves", ctypes.c_int32)]
 
 
+class muca_batch_tuning(ctypes.Structure):
+    _fields_ = [("us_per_sweep", (ctypes.c_double * 2) * 2), ("lanes_per_chain", ctypes.c_int32),
+                ("table_in_lds", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("rejected", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"us_per_sweep": {f"{l}_lanes": {"global": self.us_per_sweep[o][0], "lds": self.us_per_sweep[o][1]}
+                                 for o, l in ((0, 4), (1, 16))},
+                "lanes_per_chain": self.lanes_per_chain, "table_in_lds": self.table_in_lds,
+                "from_cache": bool(self.from_cache), "rejected": self.rejected}
+
+
 class muca_iter_stats(ctypes.Structure):
     _fields_ = [("iteration", ctypes.c_int64), ("sweeps", ctypes.c_int64), ("samples", ctypes.c_int64),
                 ("flatness", ctypes.c_double), ("flat", ctypes.c_int32), ("lo_visited", ctypes.c_int32),
@@ -67,6 +78,8 @@ def _load():
         "muca_run_iteration": (ctypes.c_int, [vp, i64, vp]),
         "muca_thermalize": (ctypes.c_int, [vp, i64, vp]),
         "muca_merge_update": (ctypes.c_int, [vp, P(muca_iter_stats)]),
+        "muca_merge_begin": (ctypes.c_int, [vp]),
+        "muca_merge_finish": (ctypes.c_int, [vp, P(muca_iter_stats)]),
         "muca_get_pending_hist": (ctypes.c_int, [vp, vp, i64]),
         "muca_merge_update_hist": (ctypes.c_int, [vp, vp, i64, P(muca_iter_stats)]),
         "muca_reweight": (ctypes.c_int, [vp, vp, i32, vp]),
@@ -81,6 +94,7 @@ def _load():
         "muca_batch_run_iteration": (ctypes.c_int, [vp, P(vp), i32, P(ctypes.c_int64), vp]),
         "muca_batch_free": (None, [vp]),
         "muca_batch_run_iteration_noalloc": (ctypes.c_int, [P(vp), i32, P(ctypes.c_int64), i32, vp]),
+        "muca_batch_tune": (ctypes.c_int, [vp, i64, vp, P(muca_batch_tuning)]),
         "muca_autotune": (ctypes.c_int, [P(muca_config), vp, u64, i64, vp, P(muca_config), P(ctypes.c_double)]),
         "muca_sizes": (ctypes.c_int, [vp, P(i32), P(i32), P(i32)]),
         "muca_get_lnw": (ctypes.c_int, [vp, vp, i32]),
@@ -103,12 +117,13 @@ def _load():
 
 LIB = _load()
 EXPORTED = ("muca_config_default", "muca_workspace_bytes", "muca_init", "muca_run_iteration",
-            "muca_thermalize", "muca_merge_update", "muca_get_pending_hist", "muca_merge_update_hist",
+            "muca_thermalize", "muca_merge_update", "muca_merge_begin", "muca_merge_finish",
+            "muca_get_pending_hist", "muca_merge_update_hist",
             "muca_reweight", "muca_blocks_shape", "muca_run_iteration_blocks", "muca_reweight_jackknife",
             "muca_em_shape", "muca_run_iteration_em", "muca_reweight_em",
             "muca_batch_workspace_bytes",
             "muca_batch_create", "muca_batch_run_iteration", "muca_batch_free",
-            "muca_batch_run_iteration_noalloc", "muca_autotune", "muca_sizes", "muca_get_lnw", "muca_get_last_hist",
+            "muca_batch_run_iteration_noalloc", "muca_batch_tune", "muca_autotune", "muca_sizes", "muca_get_lnw", "muca_get_last_hist",
             "muca_get_thresholds", "muca_get_chain_state", "muca_set_lnw", "muca_set_thresholds",
             "muca_checkpoint", "muca_restore", "muca_free", "muca_last_error")
 
@@ -152,6 +167,7 @@ class Run:
         import torch
         self.cfg = cfg
         self.stream = stream
+        self.batch_tuning = None  # set by batch_tune
         nbytes = muca_workspace_bytes(cfg)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         base = self.workspace.data_ptr()
@@ -238,6 +254,16 @@ class Run:
         _check(LIB.muca_merge_update(self.handle, ctypes.byref(st)))
         return st.as_dict()
 
+    def merge_begin(self):
+        """Enqueues the histogram read-back of the iteration (returns at once)."""
+        _check(LIB.muca_merge_begin(self.handle))
+
+    def merge_finish(self) -> dict:
+        """Waits for the read-back only, then recursion and new thresholds."""
+        st = muca_iter_stats()
+        _check(LIB.muca_merge_finish(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
     def pending_hist(self) -> np.ndarray:
         """Histogram of the sweeps since the last merge (a shard's part)."""
         h = np.zeros(self.n_bins, np.uint64)
@@ -322,12 +348,26 @@ class Run:
             pass
 
 
+def batch_tune(run: Run, probe_sweeps: int = 0, stream=None) -> dict:
+    """Measures (or reads from MUCA_AUTOTUNE_CACHE) one batched work item's
+    time for each lanes-per-chain / table-placement candidate of the run's
+    class; the run keeps it for later batched launches."""
+    t = muca_batch_tuning()
+    _check(LIB.muca_batch_tune(run.handle, int(probe_sweeps), _stream_handle(stream or run.stream), ctypes.byref(t)))
+    run.batch_tuning = t.as_dict()
+    return run.batch_tuning
+
+
 class Batch:
-    """Persistent batched launches over several lattice runs (workspace tensor kept alive)."""
+    """Persistent batched launches over several lattice runs (workspace tensor
+    kept alive).  autotune=True tunes every run's class (batch_tune) before
+    its first batched launch, so that lanes per chain, table placement and
+    the item order come from measured item times."""
 
     def __init__(self, max_runs: int, max_items: int = 8192, lanes_per_chain: int = 0,
-                 use_graph: bool = True, device="cuda"):
+                 use_graph: bool = True, device="cuda", autotune: bool = False):
         import torch
+        self.autotune = autotune
         n = ctypes.c_uint64(0)
         _check(LIB.muca_batch_workspace_bytes(max_runs, max_items, ctypes.byref(n)))
         self.workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
@@ -338,6 +378,10 @@ class Batch:
 
     def run_iteration(self, runs, sweeps, stream=None):
         n = len(runs)
+        if self.autotune:
+            for r in runs:
+                if r.batch_tuning is None:
+                    batch_tune(r, stream=stream)
         handles = (ctypes.c_void_p * n)(*[r.handle.value for r in runs])
         sw = (ctypes.c_int64 * n)(*[int(s) for s in (sweeps if np.ndim(sweeps) else [sweeps] * n)])
         _check(LIB.muca_batch_run_iteration(self.handle, handles, n, sw, _stream_handle(stream)))

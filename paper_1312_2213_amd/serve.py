@@ -4,13 +4,16 @@ Requests (a lattice model, L, q, chains and seed) arrive over time.  A
 request is admitted as soon as its device footprint (muca_workspace_bytes)
 fits in the HBM budget and its chains fit in the chain-slot budget; its
 chain state and weights then stay resident on the device until it retires.
-Every round is ONE persistent batched launch over all admitted requests:
-each advances by a chunk of sweeps sized so that a round costs about the
-same number of site updates per chain for every request (small lattices do
-not wait behind large ones).  When a request has run the sweeps of its
-current iteration, the iteration is merged (muca_merge_update: histogram
-merge, flatness, accumulated-statistics recursion, new thresholds); the
-request retires when its histogram is flat or after max_iters iterations.
+Every round is ONE persistent batched launch over the admitted requests
+that are not being merged: each advances by a chunk of sweeps sized so that
+a round costs about the same number of site updates per chain for every
+request (small lattices do not wait behind large ones).  When a request has
+run the sweeps of its current iteration, the read-back of its merged
+histogram is queued behind that round (muca_merge_begin); the next round is
+launched without it, and the host part of its merge (flatness,
+accumulated-statistics recursion, new thresholds: muca_merge_finish) runs
+while that round is on the device.  The request rejoins the round after, and
+retires when its histogram is flat or after max_iters iterations.
 
 Chunking only moves launch boundaries, so every request's result is
 bit-identical to running it alone.
@@ -88,7 +91,8 @@ class _Active:
 class Server:
     def __init__(self, hbm_budget: int = 64 << 20, chain_slots: int = 1 << 16,
                  round_site_updates: int = 1 << 16, lanes_per_chain: int = 0, use_graph: bool = True,
-                 max_active: int = 256, keep_results: bool = False, stream=None, log=None, on_round=None):
+                 max_active: int = 256, keep_results: bool = False, stream=None, log=None, on_round=None,
+                 autotune: bool = False):
         import torch
         self.hbm_budget = hbm_budget
         self.chain_slots = chain_slots
@@ -96,13 +100,14 @@ class Server:
         self.keep = keep_results
         self.stream = stream or torch.cuda.Stream()
         self.batch = muca.Batch(max_active, max_items=1 << 15, lanes_per_chain=lanes_per_chain,
-                                use_graph=use_graph)
+                                use_graph=use_graph, autotune=autotune)
         self.max_active = max_active
         self.log = log  # called with each Result as its request retires
         self.on_round = on_round  # called with (rounds so far, active requests) after each round
         self.rounds = 0
         self.peak_active = 0
         self.peak_mem = 0
+        self.overlapped_merges = 0  # merges whose host part ran while a round was on the device
 
     def _chunk(self, a: _Active) -> int:
         per_round = max(1, self.round_site_updates // (a.req.L * a.req.L))
@@ -114,7 +119,8 @@ class Server:
         import torch
         pending = sorted(requests, key=lambda r: (r.arrival, r.id))
         queue: list[Request] = []
-        active: list[_Active] = []
+        ready: list[_Active] = []    # admitted, taking part in the next round
+        merging: list[_Active] = []  # read-back queued behind the last round
         results: dict[int, Result] = {}
         used_mem = 0
         used_chains = 0
@@ -123,43 +129,55 @@ class Server:
         def now():
             return time.perf_counter() - t0
 
-        while pending or queue or active:
+        while pending or queue or ready or merging:
             t = now()
             while pending and (not realtime or pending[0].arrival <= t):
                 queue.append(pending.pop(0))
             # admission, first come first served
-            while queue and len(active) < self.max_active:
+            while queue and len(ready) + len(merging) < self.max_active:
                 req = queue[0]
                 cfg = req.config()
                 fp = muca.muca_workspace_bytes(cfg)
-                if active and (used_mem + fp > self.hbm_budget or used_chains + req.chains > self.chain_slots):
+                if (ready or merging) and (used_mem + fp > self.hbm_budget
+                                           or used_chains + req.chains > self.chain_slots):
                     break
                 queue.pop(0)
                 with torch.cuda.stream(self.stream):
                     run = muca.Run(cfg, stream=self.stream)
                 res = Result(req.id, req.arrival if realtime else 0.0, admitted=now())
                 results[req.id] = res
-                active.append(_Active(req, run, fp, res))
+                ready.append(_Active(req, run, fp, res))
                 used_mem += fp
                 used_chains += req.chains
-            self.peak_active = max(self.peak_active, len(active))
+            self.peak_active = max(self.peak_active, len(ready) + len(merging))
             self.peak_mem = max(self.peak_mem, used_mem)
-            if not active:
+            if not ready and not merging:
                 if pending:
                     time.sleep(max(0.0, min(0.01, pending[0].arrival - now())))
                 continue
-            chunks = [self._chunk(a) for a in active]
-            with torch.cuda.stream(self.stream):
-                self.batch.run_iteration([a.run for a in active], chunks, stream=self.stream)
-            self.rounds += 1
-            still = []
-            for a, ch in zip(active, chunks):
-                a.done_in_iter += ch
-                a.res.attempts += ch * a.req.chains * a.req.L * a.req.L
-                if a.done_in_iter < a.req.sweeps_per_iter:
-                    still.append(a)
-                    continue
-                st = a.run.merge_update()
+            # 1. one round for the requests not being merged (returns once enqueued)
+            began = []
+            if ready:
+                chunks = [self._chunk(a) for a in ready]
+                with torch.cuda.stream(self.stream):
+                    self.batch.run_iteration([a.run for a in ready], chunks, stream=self.stream)
+                self.rounds += 1
+                still = []
+                for a, ch in zip(ready, chunks):
+                    a.done_in_iter += ch
+                    a.res.attempts += ch * a.req.chains * a.req.L * a.req.L
+                    if a.done_in_iter < a.req.sweeps_per_iter:
+                        still.append(a)
+                    else:
+                        a.run.merge_begin()  # read-back queued behind this round
+                        began.append(a)
+                ready = still
+            # 2. the merges begun one round earlier: their read-back precedes the
+            #    round just launched, so this host work overlaps it
+            if ready and merging:
+                self.overlapped_merges += len(merging)
+            for a in merging:
+                st = a.run.merge_finish()
                 a.done_in_iter = 0
                 a.res.iterations += 1
                 a.res.flatness = st["flatness"]
@@ -175,10 +193,10 @@ class Server:
                     used_mem -= a.footprint
                     used_chains -= a.req.chains
                 else:
-                    still.append(a)
-            active = still
+                    ready.append(a)
+            merging = began
             if self.on_round:
-                self.on_round(self.rounds, len(active))
+                self.on_round(self.rounds, len(ready) + len(merging))
         torch.cuda.synchronize()
         return [results[r.id] for r in sorted(requests, key=lambda r: r.id)]
 

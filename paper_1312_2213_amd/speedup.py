@@ -131,9 +131,13 @@ def run(system: System, ps: list[int], replicas: int, seed0: int = 1, flat: floa
     live = list(range(len(runs)))
     n = [0] * len(runs)
     t0 = time.perf_counter()
+    rounds = 0
     while live:
         with torch.cuda.stream(stream):
             batch.run_iteration([runs[i] for i in live], [specs[i][1] for i in live], stream=stream)
+        rounds += 1
+        if log and rounds % 50 == 0:
+            log(f"{system.name}: round {rounds}, {len(live)} runs left, {time.perf_counter() - t0:.0f} s")
         nxt = []
         for i in live:
             st = runs[i].merge_update()

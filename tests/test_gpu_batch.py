@@ -164,3 +164,78 @@ def test_autotune_returns_valid_variant(tmp_path, monkeypatch):
         r.merge_update()
     assert np.array_equal(a.last_hist(), b.last_hist())
     assert np.array_equal(a.chain_state()[0], b.chain_state()[0])
+
+
+def test_autotuned_batch_equals_plain_and_oracle(tmp_path, monkeypatch):
+    """Lanes per chain, table placement and item order from measured item
+    times (muca_batch_tune): the tuned batch still reproduces plain launches
+    and the oracle; tuning leaves a run's results unchanged; a second run of
+    the same class reads the cache."""
+    import torch
+    from oracle import oracle as orc
+    from paper_1312_2213_amd import muca
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("MUCA_AUTOTUNE_CACHE", str(cache))
+    mid = {"ising": orc.ISING, "potts": orc.POTTS, "muma": orc.MUMA}
+    stream = torch.cuda.Stream()
+    plain = [make(s) for s in MIX]
+    tuned = [make(s) for s in MIX]
+    oracle = [orc.LatticeRun(mid[m], L, c, seed, q=q, beta=0.5 if m == "muma" else 0.0)
+              for m, L, q, c, seed, _, _ in MIX]
+    batch = muca.Batch(len(MIX), lanes_per_chain=0, use_graph=True, autotune=True)
+    sweeps = [s[-1] for s in MIX]
+    for it in range(3):
+        print(f"  iteration {it}", flush=True)
+        for r, sw in zip(plain, sweeps):
+            r.run_iteration(sw)
+            r.merge_update()
+        with torch.cuda.stream(stream):
+            batch.run_iteration(tuned, sweeps, stream=stream)
+        for k, (g, p, o, sw) in enumerate(zip(tuned, plain, oracle, sweeps)):
+            H, _, _ = o.iterate(sw)
+            g.merge_update()
+            assert np.array_equal(g.last_hist(), H) and np.array_equal(p.last_hist(), H), (it, k)
+            assert np.array_equal(g.lnw(), p.lnw()), (it, k)
+            sg, bg = snapshot(g)[2:]
+            assert np.array_equal(sg, o.spins) and np.array_equal(bg, o.bins()), (it, k)
+    for r in tuned:
+        t = r.batch_tuning
+        assert t["rejected"] == 0 and not t["from_cache"], t
+        assert t["lanes_per_chain"] in (4, 16)
+        for lanes in ("4_lanes", "16_lanes"):
+            assert t["us_per_sweep"][lanes]["global"] > 0, t
+    assert "batch/" in cache.read_text()
+    again = make(MIX[0])
+    assert muca.batch_tune(again)["from_cache"]
+
+
+def test_autotuned_round_no_slower_than_the_rule():
+    """A round of a mixed batch shaped like the batched workload (Potts
+    q = 8, L = 16 ... 48, plus multimagnetic L = 32) with the tuned choices
+    takes no longer than with the untuned rule (5 % tolerance for timing
+    noise; the minimum of four rounds each)."""
+    import time
+    import torch
+    from paper_1312_2213_amd import muca
+    specs = [("potts", 16, 8, 512, 61, 2, 20), ("potts", 32, 8, 512, 62, 2, 30),
+             ("potts", 48, 8, 512, 63, 2, 40), ("muma", 32, 2, 256, 64, 2, 30)]
+    stream = torch.cuda.Stream()
+    ms = {}
+    for mode in ("rule", "tuned"):
+        runs = [make(s) for s in specs]
+        batch = muca.Batch(len(runs), lanes_per_chain=0, use_graph=True, autotune=mode == "tuned")
+        best = None
+        for k in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            with torch.cuda.stream(stream):
+                batch.run_iteration(runs, [s[-1] for s in specs], stream=stream)
+            stream.synchronize()
+            dt = time.perf_counter() - t0
+            for r in runs:
+                r.merge_update()
+            if k:
+                best = dt if best is None else min(best, dt)
+        ms[mode] = best * 1e3
+    print(f"  round: rule {ms['rule']:.2f} ms, tuned {ms['tuned']:.2f} ms", flush=True)
+    assert ms["tuned"] <= 1.05 * ms["rule"], ms

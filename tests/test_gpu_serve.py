@@ -38,6 +38,7 @@ def test_each_result_same_alone_in_the_mix_and_in_the_oracle():
     mixed = srv.serve(reqs(), realtime=True)
     assert srv.rounds > len(mixed)  # chunked: several rounds per iteration
     assert srv.peak_active >= 2     # work of several requests overlapped on the device
+    assert srv.overlapped_merges > 0  # host merges ran while a round was on the device
     for r, req in zip(mixed, reqs()):
         print(f"  request {req.id}: {req.model} L={req.L} q={req.q} chains={req.chains}", flush=True)
         alone = run_alone(req)
