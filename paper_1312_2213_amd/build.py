@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmuca.so")
 
 SOURCES = ["lattice_ising.hip", "lattice_muma.hip", "lattice_potts.hip", "lattice_common.hip",
-           "polymer.hip", "batch.hip", "runtime.cpp", "polymer_host.cpp", "autotune.cpp"]
+           "polymer.hip", "batch.hip", "runtime.cpp", "host_math.cpp", "polymer_host.cpp", "autotune.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
           "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]

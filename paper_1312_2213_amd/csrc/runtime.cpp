@@ -147,196 +147,9 @@ int muca_geometry(const muca_config *c, Geometry *g)
     return MUCA_OK;
 }
 
-// Values of the binned quantity that no lattice configuration takes
-// (Omega = 0 on the even-L torus): Ising E = +-(2N - 4); Potts q = 2 odd
-// E_unsat and E_unsat in {2, 2N - 2}; Potts q >= 3 E_unsat in {1, 2, 3, 5}.
-// The recursion links consecutive bins of the remaining set and flatness is
-// measured over it.
-static void reachable_mask(const muca_config *c, const Geometry &g, std::vector<uint8_t> &m)
-{
-    m.assign(g.n_bins, 1);
-    const int N = g.n_sites;
-    for (int b = 0; b < g.n_bins; ++b) {
-        const int v = c->lo + b * g.step;
-        if (g.model == kIsing) {
-            if (v == 2 * N - 4 || v == -(2 * N - 4))
-                m[b] = 0;
-        } else if (g.model == kPotts) {
-            if (c->q == 2) {
-                if ((v % 2) != 0 || v == 2 || v == 2 * N - 2)
-                    m[b] = 0;
-            } else if (v == 1 || v == 2 || v == 3 || v == 5) {
-                m[b] = 0;
-            }
-        }
-    }
-}
 
-// min(1, exp(D)) as an integer threshold on a uniform 32-bit word r: accept
-// iff r < T, with T = 0xffffffff meaning "always".
-static uint32_t threshold_of(double D)
-{
-    if (D >= 0.0)
-        return 0xffffffffu;
-    // 2^32 e^D < 1 for D < -32 ln 2 = -22.18: the threshold is 0, no exp needed
-    if (D < -23.0)
-        return 0u;
-    const double v = std::exp(D) * 4294967296.0; // times 2^32: exact
-    if (v >= 4294967295.0)
-        return 0xffffffffu;
-    return (uint32_t)std::floor(v);
-}
 
-uint32_t muca_threshold_of(double D) { return threshold_of(D); }
 
-static void build_lattice_thresholds(const muca_config *c, const Geometry &g, const double *lnW,
-                                     uint32_t *T)
-{
-    const int B = g.n_bins, NC = g.n_cols;
-    for (int b = 0; b < B; ++b) {
-        for (int j = 0; j < NC; ++j) {
-            int target;
-            double D;
-            if (g.model == kIsing) {
-                target = b + j - 2; // column = aligned neighbours, dE = 4j - 8
-            } else if (g.model == kPotts) {
-                target = b + j - 4; // column = dE_unsat + 4
-            } else {
-                target = (j & 1) ? b - 1 : b + 1; // column = 2 n_aligned + (s_i == +1)
-            }
-            if (target < 0 || target >= B) {
-                T[(size_t)b * NC + j] = 0u;
-                continue;
-            }
-            D = lnW[target] - lnW[b];
-            if (g.model == kMuma) {
-                const int dE = 4 * (j >> 1) - 8;
-                D = D - c->beta * (double)dE;
-            }
-            T[(size_t)b * NC + j] = threshold_of(D);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Accumulated-statistics recursion on consecutive bins of the set `m`:
-//   p = h0 h1 / (h0 + h1) (0 if a bin is empty),  P += p,
-//   lnR += (p / P) (ln h0 - ln h1),
-// then lnW is the running sum of lnR from the first bin of the set (lnW = 0
-// there); bins outside the set repeat the last weight.
-// ---------------------------------------------------------------------------
-void muca_recursion(int B, const uint8_t *m, const uint64_t *H, double *lnR, double *P, double *lnW)
-{
-    int lower = -1;
-    for (int b = 0; b < B; ++b) {
-        if (!m[b])
-            continue;
-        if (lower >= 0) {
-            const uint64_t a = H[lower], c = H[b];
-            double p = 0.0;
-            if (a != 0 && c != 0) {
-                const double h0 = (double)a, h1 = (double)c;
-                p = (h0 * h1) / (h0 + h1);
-            }
-            P[lower] = P[lower] + p;
-            if (p > 0.0) {
-                const double kappa = p / P[lower];
-                lnR[lower] = lnR[lower] + kappa * (std::log((double)a) - std::log((double)c));
-            }
-        }
-        lower = b;
-    }
-    double run = 0.0;
-    int last = -1;
-    for (int b = 0; b < B; ++b) {
-        if (m[b]) {
-            if (last >= 0)
-                run = run + lnR[last];
-            last = b;
-        }
-        lnW[b] = run;
-    }
-}
-
-double muca_flatness(int B, const uint8_t *m, const uint64_t *H)
-{
-    double lo = 0.0, sum = 0.0;
-    int n = 0;
-    for (int b = 0; b < B; ++b) {
-        if (!m[b])
-            continue;
-        const double h = (double)H[b];
-        if (n == 0 || h < lo)
-            lo = h;
-        sum += h;
-        ++n;
-    }
-    if (n == 0 || sum <= 0.0)
-        return 0.0;
-    return lo / (sum / (double)n);
-}
-
-// Reweighting, Eq. 2, on the binned histogram.  Sums in ascending bin order.
-void muca_reweight_bins(int B, const uint64_t *H, const double *lnW, const double *val, int nsite,
-                        bool muma, double beta, double *out)
-{
-    double amax = 0.0;
-    bool any = false;
-    for (int b = 0; b < B; ++b) {
-        if (!H[b])
-            continue;
-        double a = std::log((double)H[b]) - lnW[b];
-        if (!muma)
-            a = a - beta * val[b];
-        if (!any || a > amax)
-            amax = a;
-        any = true;
-    }
-    if (!any) {
-        out[0] = out[1] = out[2] = out[3] = 0.0;
-        return;
-    }
-    double Z = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (int b = 0; b < B; ++b) {
-        if (!H[b])
-            continue;
-        double a = std::log((double)H[b]) - lnW[b];
-        if (!muma)
-            a = a - beta * val[b];
-        const double w = std::exp(a - amax);
-        Z += w;
-        if (muma) {
-            s1 += w * std::fabs(val[b]);
-            s2 += w * (val[b] * val[b]);
-            s3 += w * val[b];
-        } else {
-            s1 += w * val[b];
-        }
-    }
-    const double n = (double)nsite;
-    if (muma) {
-        out[0] = (s1 / Z) / n;
-        out[1] = (s2 / Z) / (n * n);
-        out[2] = (s3 / Z) / n;
-        out[3] = amax + std::log(Z);
-        return;
-    }
-    const double mean = s1 / Z;
-    double var = 0.0;
-    for (int b = 0; b < B; ++b) {
-        if (!H[b])
-            continue;
-        const double a = std::log((double)H[b]) - lnW[b] - beta * val[b];
-        const double w = std::exp(a - amax);
-        const double d = val[b] - mean;
-        var += w * (d * d);
-    }
-    var = var / Z;
-    out[0] = mean / n;
-    out[1] = (beta * beta) * var / n;
-    out[2] = mean;
-    out[3] = amax + std::log(Z);
-}
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -431,7 +244,7 @@ int muca_rebuild_thresholds(muca_run *r)
     if (r->g.model == kPolymer)
         muca_polymer_build(r);
     else
-        build_lattice_thresholds(&r->cfg, r->g, r->lnW.data(), r->T.data());
+        muca_lattice_thresholds(r->g.model, r->cfg.beta, r->g.n_bins, r->g.n_cols, r->lnW.data(), r->T.data());
     return muca_upload_thresholds(r);
 }
 
@@ -499,7 +312,8 @@ try {
         *out = r;
         return MUCA_OK;
     }
-    reachable_mask(c, g, r->mask);
+    r->mask.assign(g.n_bins, 1);
+    muca_reachable_mask(g.model, c->q, c->lo, g.step, g.n_sites, g.n_bins, r->mask.data());
     try {
         r->T.assign((size_t)g.n_bins * g.n_cols, 0u);
     } catch (const std::bad_alloc &) {
@@ -863,59 +677,6 @@ try {
 }
 MUCA_ABI_CATCH
 
-// Canonical averages at beta2 from the joint histogram of a multimagnetic run
-// at beta with log weights lnW: each state's canonical weight relative to its
-// sampling weight exp(-beta E) W(M) is exp(-(beta2 - beta) E) / W(M).
-static void reweight_joint(int NE, int B, const uint64_t *h, const double *lnW, int32_t lo, int32_t mstep,
-                           int nsite, double beta, double beta2, double *out)
-{
-    auto energy = [&](int e) { return -2.0 * nsite + 4.0 * e; };
-    auto magnet = [&](int b) { return (double)lo + (double)mstep * b; };
-    auto log_w = [&](int e, int b) {
-        return std::log((double)h[(size_t)e * B + b]) - lnW[b] - (beta2 - beta) * energy(e);
-    };
-    double amax = 0.0;
-    bool any = false;
-    for (int e = 0; e < NE; ++e)
-        for (int b = 0; b < B; ++b)
-            if (h[(size_t)e * B + b]) {
-                const double a = log_w(e, b);
-                if (!any || a > amax)
-                    amax = a;
-                any = true;
-            }
-    if (!any) {
-        for (int k = 0; k < 6; ++k)
-            out[k] = 0.0;
-        return;
-    }
-    double Z = 0.0, sE = 0.0, sA = 0.0, s2 = 0.0;
-    for (int e = 0; e < NE; ++e)
-        for (int b = 0; b < B; ++b)
-            if (h[(size_t)e * B + b]) {
-                const double w = std::exp(log_w(e, b) - amax), m = magnet(b);
-                Z += w;
-                sE += w * energy(e);
-                sA += w * std::fabs(m);
-                s2 += w * (m * m);
-            }
-    const double mean = sE / Z;
-    double var = 0.0;
-    for (int e = 0; e < NE; ++e)
-        for (int b = 0; b < B; ++b)
-            if (h[(size_t)e * B + b]) {
-                const double w = std::exp(log_w(e, b) - amax), d = energy(e) - mean;
-                var += w * (d * d);
-            }
-    var /= Z;
-    const double n = (double)nsite, mA = sA / Z, m2 = s2 / Z;
-    out[0] = mean / n;
-    out[1] = beta2 * beta2 * var / n;
-    out[2] = mA / n;
-    out[3] = m2 / (n * n);
-    out[4] = beta2 * (m2 - mA * mA) / n;
-    out[5] = amax + std::log(Z);
-}
 
 extern "C" int muca_reweight_em(const muca_run *r, const uint64_t *h_em, int64_t n_em, const double *betas,
                                 int32_t n, double *out)
@@ -934,7 +695,7 @@ try {
     if (n < 1 || !betas || !out)
         return muca_fail(MUCA_E_ARG, "need n >= 1, betas and an output array");
     for (int k = 0; k < n; ++k)
-        reweight_joint(NE, B, h_em, r->lnW_last.data(), r->cfg.lo, g.step, g.n_sites, r->cfg.beta, betas[k],
+        muca_reweight_joint(NE, B, h_em, r->lnW_last.data(), r->cfg.lo, g.step, g.n_sites, r->cfg.beta, betas[k],
                        out + 6 * k);
     return MUCA_OK;
 }

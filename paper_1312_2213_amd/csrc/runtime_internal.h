@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/muca.h"
+#include "host_math.h"
 
 namespace muca {
 
@@ -128,9 +129,6 @@ int muca_use_stream(muca_run *r, hipStream_t s);
 int muca_enqueue_sweeps(muca_run *r, int64_t sweeps, bool record, hipStream_t s,
                         unsigned long long *em = nullptr, unsigned long long *hist_blocks = nullptr);
 int muca_finish_iteration(muca_run *r, const uint64_t *H, uint64_t accepted, muca_iter_stats *st);
-uint32_t muca_threshold_of(double D);
-void muca_recursion(int B, const uint8_t *m, const uint64_t *H, double *lnR, double *P, double *lnW);
-double muca_flatness(int B, const uint8_t *m, const uint64_t *H);
 
 // polymer.cpp
 int muca_polymer_geometry(const muca_config *c, muca::Geometry *g);
