@@ -106,6 +106,8 @@ def parse():
     ap.add_argument("--replicas", type=int, default=0, help="speedup --speedup-set qscan: runs per p")
     ap.add_argument("--round-site-updates", type=int, default=1 << 16,
                     help="serving: site updates per chain in one round")
+    ap.add_argument("--overlap-min-rounds", type=int, default=None,
+                    help="serving: overlap the merges of requests whose iterations span at least this many rounds")
     return ap.parse_args()
 
 
@@ -528,10 +530,13 @@ def bench_serving(args):
                     chains=r["chains"], seed=r["seed"], max_iters=args.max_iters)
             for r in request_stream(args.requests, 4.0, 4)]
     def retired(r):
-        print(f"request {r.id}: {r.iterations} iterations, flat={r.flat}, "
-              f"time to flat {r.time_to_flat:.2f} s", file=sys.stderr, flush=True)
+        # one JSON line per request on stderr: arrival, admission, completion
+        print(json.dumps({"request": r.id, "arrival_s": r.arrival, "admitted_s": r.admitted,
+                          "finished_s": r.finished, "iterations": r.iterations, "flat": r.flat,
+                          "cancelled": r.cancelled, "time_to_flat_s": r.time_to_flat}), file=sys.stderr, flush=True)
 
-    srv = Server(hbm_budget=64 << 20, round_site_updates=args.round_site_updates, log=retired)
+    kw = {} if args.overlap_min_rounds is None else {"overlap_min_rounds": args.overlap_min_rounds}
+    srv = Server(hbm_budget=64 << 20, round_site_updates=args.round_site_updates, log=retired, **kw)
     t0 = time.perf_counter()
     res = srv.serve(reqs, realtime=True)
     s = summarize(res, time.perf_counter() - t0)
@@ -540,7 +545,10 @@ def bench_serving(args):
                           "Potts q in {2..10}, L in {16,32}; 256-2048 chains; flatness 0.5; "
                           f"max {args.max_iters} iterations; HBM budget 64 MiB; "
                           f"{args.round_site_updates} site updates per chain and round",
-              "rounds": srv.rounds, "peak_active": srv.peak_active})
+              "rounds": srv.rounds, "peak_active": srv.peak_active,
+              "overlap_min_rounds": srv.overlap_min_rounds, "overlapped_merges": srv.overlapped_merges,
+              "mean_round_ms": s["makespan_s"] / max(1, srv.rounds) * 1e3,
+              "mean_overlapped_merge_ms": srv.merge_seconds / srv.merges * 1e3 if srv.merges else None})
     return s
 
 

@@ -53,7 +53,9 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         msg = "\n".join(f"--- {s}\n{o}" for s, o in failed)
         raise RuntimeError("hipcc failed:\n" + msg)
     tmp = LIB + ".tmp"
-    subprocess.check_call([cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
+    # roctx ranges for profiler timelines (rocprofiler-sdk's marker library)
+    subprocess.check_call([cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,
+                           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -531,6 +531,7 @@ static void advance_runs(muca_run *const *runs, int n, const int64_t *sweeps)
 extern "C" int muca_batch_run_iteration(muca_batch *b, muca_run *const *runs, int32_t n, const int64_t *sweeps,
                                         void *stream)
 try {
+    RoctxRange range("muca_batch_round");
     if (!b || !runs || !sweeps || n < 1)
         return muca_fail(MUCA_E_ARG, "bad arguments");
     if (b->poisoned)
@@ -635,6 +636,7 @@ static int scratch_address(uint8_t **out)
 extern "C" int muca_batch_run_iteration_noalloc(muca_run *const *runs, int32_t n, const int64_t *sweeps,
                                                 int32_t lanes_per_chain, void *stream)
 try {
+    RoctxRange range("muca_batch_round_noalloc");
     if (!runs || !sweeps || n < 1)
         return muca_fail(MUCA_E_ARG, "bad arguments");
     if (n > kScratchRuns)
@@ -762,6 +764,7 @@ static uint64_t fnv1a64(uint64_t h, const void *p, size_t n)
 
 extern "C" int muca_batch_tune(muca_run *r, int64_t probe_sweeps, void *stream, muca_batch_tuning *out)
 try {
+    RoctxRange range("muca_batch_tune");
     if (!r || r->poisoned)
         return muca_fail(MUCA_E_STATE, "null or poisoned run");
     if (r->merge_begun)

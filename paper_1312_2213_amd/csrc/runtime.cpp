@@ -14,11 +14,17 @@
 
 #include <algorithm>
 #include <cmath>
+#include <atomic>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "../../include/muca.h"
 #include "muca_internal.h"
@@ -41,6 +47,39 @@ int muca_fail(int code, const char *fmt, ...)
 }
 
 const char *muca_last_error(void) { return g_last_error; }
+
+RoctxRange::RoctxRange(const char *name) { roctxRangePushA(name); }
+RoctxRange::~RoctxRange() { roctxRangePop(); }
+
+static double wall_seconds()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static std::atomic<int64_t> g_run_ids{0};
+static std::mutex g_log_mutex;
+
+void muca_log_iteration(const muca_run *r, const muca_iter_stats &s, double seconds, double attempts)
+{
+    const char *path = std::getenv("MUCA_ITER_LOG");
+    if (!path || !*path)
+        return;
+    static const char *names[] = {"ising", "potts", "muma", "polymer"};
+    std::lock_guard<std::mutex> lock(g_log_mutex);
+    FILE *f = std::fopen(path, "a");
+    if (!f)
+        return;
+    std::fprintf(f,
+                 "{\"run\": %lld, \"model\": \"%s\", \"L\": %d, \"q\": %d, \"n_beads\": %d, \"chains\": %d, "
+                 "\"seed\": %llu, \"iteration\": %lld, \"sweeps\": %lld, \"samples\": %lld, \"flatness\": %.17g, "
+                 "\"flat\": %d, \"lo_visited\": %d, \"hi_visited\": %d, \"accept_rate\": %.17g, "
+                 "\"seconds\": %.6f, \"attempts_per_s\": %.6g}\n",
+                 (long long)r->log_id, names[r->g.model & 3], r->cfg.L, r->cfg.q, r->cfg.n_beads, r->cfg.n_chains,
+                 (unsigned long long)r->cfg.seed, (long long)s.iteration, (long long)s.sweeps, (long long)s.samples,
+                 s.flatness, s.flat, s.lo_visited, s.hi_visited, s.accept_rate, seconds,
+                 seconds > 0.0 ? attempts / seconds : 0.0);
+    std::fclose(f);
+}
 
 static size_t align256(size_t x) { return (x + 255u) & ~(size_t)255u; }
 
@@ -276,7 +315,10 @@ try {
             }
         }
     }
+    RoctxRange range("muca_init");
     muca_run *r = new muca_run();
+    r->log_id = ++g_run_ids;
+    r->t_last = wall_seconds();
     r->cfg = *c;
     r->g = g;
     r->stream = (hipStream_t)stream;
@@ -411,6 +453,7 @@ int muca_use_stream(muca_run *r, hipStream_t s)
 
 extern "C" int muca_run_iteration(muca_run *r, int64_t sweeps, void *stream)
 try {
+    RoctxRange range("muca_run_iteration");
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -551,6 +594,9 @@ int muca_finish_iteration(muca_run *r, const uint64_t *H, uint64_t accepted, muc
         muca_recursion(B, r->mask.data(), H, r->lnR.data(), r->P.data(), r->lnW.data());
     }
     s.flat = s.flatness > r->cfg.flat_threshold ? 1 : 0;
+    const double now = wall_seconds();
+    muca_log_iteration(r, s, now - r->t_last, (double)r->pending * (double)r->cfg.n_chains * per_sweep);
+    r->t_last = now;
     r->iteration += 1;
     r->pending = 0;
     r->have_last = true;
@@ -563,6 +609,7 @@ int muca_finish_iteration(muca_run *r, const uint64_t *H, uint64_t accepted, muc
 
 extern "C" int muca_merge_begin(muca_run *r)
 try {
+    RoctxRange range("muca_merge_begin");
     int rc = check_run(r);
     if (rc)
         return rc;
@@ -584,6 +631,7 @@ MUCA_ABI_CATCH
 
 extern "C" int muca_merge_finish(muca_run *r, muca_iter_stats *st)
 try {
+    RoctxRange range("muca_merge_finish");
     if (!r)
         return muca_fail(MUCA_E_ARG, "null run");
     if (r->poisoned)

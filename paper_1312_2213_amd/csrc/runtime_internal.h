@@ -88,10 +88,27 @@ struct muca_run {
     // recorded behind the histogram read-back, and whether one is under way
     hipEvent_t merge_ev = nullptr;
     bool merge_begun = false;
+    // per-iteration log: this run's number and the wall clock of its last merge
+    int64_t log_id = 0;
+    double t_last = 0.0;
     ~muca_run();
 };
 
 int muca_fail(int code, const char *fmt, ...);
+
+// A named range on the roctx timeline of a profiler (rocprofv3
+// --marker-trace): init, iterations, merges and batched rounds show up
+// beside the kernels.  Costs a function call when no profiler listens.
+struct RoctxRange {
+    explicit RoctxRange(const char *name);
+    ~RoctxRange();
+    RoctxRange(const RoctxRange &) = delete;
+    RoctxRange &operator=(const RoctxRange &) = delete;
+};
+
+// One JSON line per merged iteration, appended to the file named by the
+// environment variable MUCA_ITER_LOG (nothing when it is unset).
+void muca_log_iteration(const muca_run *r, const muca_iter_stats &s, double seconds, double attempts);
 
 // A HIP call whose failure poisons the run and returns MUCA_E_HIP.
 #define HIP_OR_POISON(run, expr)                                                                   \

@@ -9,10 +9,13 @@ that are not being merged: each advances by a chunk of sweeps sized so that
 a round costs about the same number of site updates per chain for every
 request (small lattices do not wait behind large ones).  When a request has
 run the sweeps of its current iteration, the read-back of its merged
-histogram is queued behind that round (muca_merge_begin); the next round is
-launched without it, and the host part of its merge (flatness,
-accumulated-statistics recursion, new thresholds: muca_merge_finish) runs
-while that round is on the device.  The request rejoins the round after, and
+histogram is queued behind that round (muca_merge_begin).  A request whose
+iterations span at least `overlap_min_rounds` rounds is left out of the
+next round, and the host part of its merge (flatness, accumulated-statistics
+recursion, new thresholds: muca_merge_finish) runs while that round is on
+the device; it rejoins the round after (one skipped round per iteration, a
+small share of a long iteration).  A request with shorter iterations is
+merged before the next round is launched, so it never skips one.  A request
 retires when its histogram is flat or after max_iters iterations.
 
 Chunking only moves launch boundaries, so every request's result is
@@ -74,6 +77,7 @@ class Result:
     flat: bool = False
     flatness: float = 0.0
     attempts: int = 0
+    cancelled: bool = False
     lnw: np.ndarray | None = field(default=None, repr=False)
     hist: np.ndarray | None = field(default=None, repr=False)
 
@@ -92,8 +96,9 @@ class Server:
     def __init__(self, hbm_budget: int = 64 << 20, chain_slots: int = 1 << 16,
                  round_site_updates: int = 1 << 16, lanes_per_chain: int = 0, use_graph: bool = True,
                  max_active: int = 256, keep_results: bool = False, stream=None, log=None, on_round=None,
-                 autotune: bool = False):
+                 autotune: bool = False, overlap_min_rounds: int = 4):
         import torch
+        self.overlap_min_rounds = overlap_min_rounds
         self.hbm_budget = hbm_budget
         self.chain_slots = chain_slots
         self.round_site_updates = round_site_updates
@@ -108,10 +113,26 @@ class Server:
         self.peak_active = 0
         self.peak_mem = 0
         self.overlapped_merges = 0  # merges whose host part ran while a round was on the device
+        self.merge_seconds = 0.0    # host time in muca_merge_finish (overlapped merges: no wait)
+        self.merges = 0
+        self._cancel: set[int] = set()
+
+    def cancel(self, request_id: int):
+        """Withdraws a request: if it is waiting it is never admitted, if it
+        runs it leaves before the next round (its device memory is freed);
+        the other requests' results are unchanged.  May be called from the
+        log or on_round callbacks."""
+        self._cancel.add(request_id)
+
+    def _per_round(self, a: _Active) -> int:
+        return max(1, self.round_site_updates // (a.req.L * a.req.L))
 
     def _chunk(self, a: _Active) -> int:
-        per_round = max(1, self.round_site_updates // (a.req.L * a.req.L))
-        return min(per_round, a.req.sweeps_per_iter - a.done_in_iter)
+        return min(self._per_round(a), a.req.sweeps_per_iter - a.done_in_iter)
+
+    def _overlapped(self, a: _Active) -> bool:
+        """Whether this request's merges overlap the next round."""
+        return -(-a.req.sweeps_per_iter // self._per_round(a)) >= self.overlap_min_rounds
 
     def serve(self, requests: list[Request], realtime: bool = True) -> list[Result]:
         """Runs the requests to completion; arrival times are seconds from start
@@ -129,10 +150,30 @@ class Server:
         def now():
             return time.perf_counter() - t0
 
+        def drop(req: Request, res: Result | None = None):
+            res = res or Result(req.id, req.arrival if realtime else 0.0, admitted=now())
+            res.cancelled = True
+            res.finished = now()
+            results[req.id] = res
+            if self.log:
+                self.log(res)
+
         while pending or queue or ready or merging:
             t = now()
             while pending and (not realtime or pending[0].arrival <= t):
                 queue.append(pending.pop(0))
+            if self._cancel:
+                for req in [r for r in pending + queue if r.id in self._cancel]:
+                    (pending if req in pending else queue).remove(req)
+                    drop(req)
+                for a in [a for a in ready if a.req.id in self._cancel]:
+                    ready.remove(a)
+                    a.run.free()
+                    used_mem -= a.footprint
+                    used_chains -= a.req.chains
+                    drop(a.req, a.res)
+                if not (pending or queue or ready or merging):
+                    break
             # admission, first come first served
             while queue and len(ready) + len(merging) < self.max_active:
                 req = queue[0]
@@ -172,12 +213,19 @@ class Server:
                         a.run.merge_begin()  # read-back queued behind this round
                         began.append(a)
                 ready = still
-            # 2. the merges begun one round earlier: their read-back precedes the
-            #    round just launched, so this host work overlaps it
+            # 2. the merges begun one round earlier (their read-back precedes the
+            #    round just launched, so this host work overlaps it), then those
+            #    of requests with short iterations (these wait for the round)
             if ready and merging:
                 self.overlapped_merges += len(merging)
-            for a in merging:
+            now_merged = [a for a in began if not self._overlapped(a)]
+            began = [a for a in began if self._overlapped(a)]
+            for a in merging + now_merged:
+                t_m = time.perf_counter()
                 st = a.run.merge_finish()
+                if a in merging:
+                    self.merge_seconds += time.perf_counter() - t_m
+                    self.merges += 1
                 a.done_in_iter = 0
                 a.res.iterations += 1
                 a.res.flatness = st["flatness"]
@@ -229,13 +277,14 @@ def summarize(results: list[Result], makespan: float) -> dict:
     requests that became flat; requests stopped by max_iters are counted
     apart, with their time to stop."""
     flat = np.array([r.time_to_flat for r in results if r.flat])
-    capped = np.array([r.time_to_flat for r in results if not r.flat])
+    capped = np.array([r.time_to_flat for r in results if not r.flat and not r.cancelled])
     attempts = sum(r.attempts for r in results)
 
     def pct(a, p):
         return float(np.percentile(a, p)) if len(a) else None
 
     return {"requests": len(results), "flat": int(len(flat)), "capped": int(len(capped)),
+            "cancelled": sum(1 for r in results if r.cancelled),
             "p50_time_to_flat_s": pct(flat, 50), "p99_time_to_flat_s": pct(flat, 99),
             "mean_time_to_flat_s": float(flat.mean()) if len(flat) else None,
             "p50_time_to_stop_capped_s": pct(capped, 50), "makespan_s": makespan,

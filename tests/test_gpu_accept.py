@@ -79,3 +79,24 @@ def test_polymer_accept_rate(moves):
         st = g.merge_update()
         assert np.array_equal(g.last_hist(), H)
         assert st["accept_rate"] == rate(o, 6, per), it
+
+
+def test_iteration_log(tmp_path, monkeypatch):
+    """MUCA_ITER_LOG: one JSON line per merged iteration with the merge's
+    statistics (flatness, visited range, acceptance) and its timing."""
+    import json
+    log = tmp_path / "iters.jsonl"
+    monkeypatch.setenv("MUCA_ITER_LOG", str(log))
+    _, g = pair("potts", 8, 64, seed=5, q=3)
+    stats = []
+    for _ in range(3):
+        g.run_iteration(7)
+        stats.append(g.merge_update())
+    rows = [json.loads(l) for l in log.read_text().splitlines()]
+    assert len(rows) == 3 and len({r["run"] for r in rows}) == 1
+    for row, st in zip(rows, stats):
+        assert row["model"] == "potts" and row["L"] == 8 and row["q"] == 3 and row["chains"] == 64
+        for k in ("iteration", "sweeps", "samples", "flat", "lo_visited", "hi_visited"):
+            assert row[k] == st[k], k
+        assert row["flatness"] == st["flatness"] and row["accept_rate"] == st["accept_rate"]
+        assert row["seconds"] > 0 and row["attempts_per_s"] > 0

@@ -66,3 +66,21 @@ def test_admission_respects_the_memory_budget():
     assert len(out) == len(rs) and all(r.iterations >= 1 for r in out)
     assert srv.peak_mem <= max(sizes)
     assert srv.peak_active < len(rs)  # the budget forced requests to wait for memory
+
+
+def test_cancelling_a_request_leaves_the_others_unchanged():
+    """A request withdrawn after a few rounds leaves at once; every other
+    request still ends with exactly the result it gets alone."""
+    from paper_1312_2213_amd.serve import Server, run_alone
+    srv = Server(hbm_budget=256 << 20, round_site_updates=4096, keep_results=True)
+    srv.on_round = lambda rounds, active: srv.cancel(2) if rounds == 3 else None
+    rs = reqs()
+    out = srv.serve(rs, realtime=False)
+    assert out[2].cancelled and not out[2].flat
+    for r, req in zip(out, rs):
+        if req.id == 2:
+            continue
+        print(f"  request {req.id}", flush=True)
+        alone = run_alone(req)
+        assert not r.cancelled and r.iterations == alone.iterations
+        assert np.array_equal(r.hist, alone.hist) and np.array_equal(r.lnw, alone.lnw), req
