@@ -71,7 +71,7 @@ class Request:
 class Result:
     id: int
     arrival: float
-    admitted: float = 0.0
+    admitted: float | None = 0.0
     finished: float = 0.0
     iterations: int = 0
     flat: bool = False
@@ -151,7 +151,8 @@ class Server:
             return time.perf_counter() - t0
 
         def drop(req: Request, res: Result | None = None):
-            res = res or Result(req.id, req.arrival if realtime else 0.0, admitted=now())
+            # a request withdrawn before admission has no admission time
+            res = res or Result(req.id, req.arrival if realtime else 0.0, admitted=None)
             res.cancelled = True
             res.finished = now()
             results[req.id] = res
@@ -198,6 +199,7 @@ class Server:
                 continue
             # 1. one round for the requests not being merged (returns once enqueued)
             began = []
+            launched = bool(ready)
             if ready:
                 chunks = [self._chunk(a) for a in ready]
                 with torch.cuda.stream(self.stream):
@@ -216,7 +218,7 @@ class Server:
             # 2. the merges begun one round earlier (their read-back precedes the
             #    round just launched, so this host work overlaps it), then those
             #    of requests with short iterations (these wait for the round)
-            if ready and merging:
+            if launched and merging:
                 self.overlapped_merges += len(merging)
             now_merged = [a for a in began if not self._overlapped(a)]
             began = [a for a in began if self._overlapped(a)]
