@@ -397,6 +397,10 @@ __device__ __forceinline__ void ilp_site(const uint64_t (&pk)[RowRng<L, LPC, 1>:
         n_t0 = load_t<TLDS>(T, B + sbyte(D));
         n_t1 = load_t<TLDS>(T, Bf + sbyte(D >> 8));
     }
+    // the previous site's flip record, while the reads are in flight: not
+    // between the threshold select and the compare
+    if constexpr (X > 0)
+        F[(X - 1) / 32] = shift_in<false>(F[(X - 1) / 32], pm);
     // selected only now, after the next reads were issued (the barrier keeps
     // the wait for this site's reads one site behind them)
     __builtin_amdgcn_sched_barrier(0);
@@ -407,8 +411,6 @@ __device__ __forceinline__ void ilp_site(const uint64_t (&pk)[RowRng<L, LPC, 1>:
     // descriptor is dead by now, and the reads above are a few instructions back)
     if constexpr (X + 1 < L)
         cur = ilp_get<L, LPC, X + 1>(pk, dv2, dv1, f0);
-    if constexpr (X > 0)
-        F[(X - 1) / 32] = shift_in<false>(F[(X - 1) / 32], pm);
     const bool acc = r < t;
     if constexpr (X == 0)
         f0 = acc;
@@ -938,6 +940,10 @@ __device__ __forceinline__ void lp_site(const uint64_t (&geo)[PottsLP<L, LPC>::S
         n_t1 = load_t<TLDS>(T, Bf + sbyte(glo >> 8));
         lp_get<L, LPC, X + 1>(geo, acw, gv2, gv1, av1, f0, ng, nw);
     }
+    // the previous site's flip record, while the reads are in flight: not
+    // between the threshold select and the compare
+    if constexpr (X > 0)
+        F[(X - 1) / 32] = shift_in<false>(F[(X - 1) / 32], pm);
     // selected only now, after the next reads were issued (the barrier keeps
     // the wait for this site's reads one site behind them)
     __builtin_amdgcn_sched_barrier(0);
@@ -946,8 +952,6 @@ __device__ __forceinline__ void lp_site(const uint64_t (&geo)[PottsLP<L, LPC>::S
     t1 = n_t1;
     g = ng;
     w = nw;
-    if constexpr (X > 0)
-        F[(X - 1) / 32] = shift_in<false>(F[(X - 1) / 32], pm);
     const bool acc = word <= t;
     if constexpr (X == 0)
         f0 = acc;
