@@ -54,8 +54,8 @@ OPS_PER_ATTEMPT = 23.0
 # by a device copy of known size, and the sha256 of the sources and flags
 # that built the profiled kernel: the figure is reported only while they are
 # unchanged.
-HBM_TRAFFIC = {"bytes_per_launch": 3454.125 * 1024 * 2.0 + 2482.125 * 1024,
-               "kernel_sources_sha256": "8f5ad3f840ab3f57"}
+HBM_TRAFFIC = {"bytes_per_launch": 3198.125 * 1024 * 2.0 + 2482.125 * 1024,
+               "kernel_sources_sha256": "f7d52b154c4c3b97"}
 KERNEL_SOURCES = ["paper_1312_2213_amd/csrc/lattice_impl.h", "paper_1312_2213_amd/csrc/muca_internal.h",
                   "paper_1312_2213_amd/csrc/philox.h", "paper_1312_2213_amd/csrc/lattice_ising.hip"]
 
@@ -84,6 +84,8 @@ def parse():
                              "speedup", "muma_em", "copy"])
     ap.add_argument("--sweeps", type=int, default=10000, help="sweeps per iteration (workload: 10^4)")
     ap.add_argument("--lanes-per-chain", type=int, default=0)
+    ap.add_argument("--chains-per-block", type=int, default=0,
+                    help="ising64: chains per block (0: the library's choice; x lanes per chain = threads)")
     ap.add_argument("--chains", type=int, default=4096, help="ising64: chains (workload: 4096)")
     ap.add_argument("--batch-lanes-per-chain", type=int, default=0, help="batched runs: 4, 16 or 0 (per run)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -404,7 +406,7 @@ def bench_ising64(args):
     torch.cuda.set_device(0)
     L, C, seed, S = 64, args.chains, 2, args.sweeps
     cfg = muca.muca_config_default("ising", L, 2, C, seed, layout=muca.MUCA_LAYOUT_BIT,
-                                   lanes_per_chain=args.lanes_per_chain)
+                                   lanes_per_chain=args.lanes_per_chain, chains_per_block=args.chains_per_block)
     stream = torch.cuda.current_stream()
     run = muca.Run(cfg, stream=stream)
     for _ in range(args.warmup):

@@ -81,7 +81,8 @@ typedef struct muca_config {
     double beta;            /* MUMA: fixed inverse temperature                 */
     double flat_threshold;  /* flat iff min(H)/mean(H) over the flatness set > this */
     int32_t chains_per_block; /* 0 = auto; chains_per_block x lanes_per_chain
-                                 must be 64, 128 or 256 threads              */
+                                 must be 64, 128, 256 or 512 threads; 512
+                                 only with the table staged in LDS         */
     int32_t table_in_lds;   /* -1 auto, 0 thresholds read from global memory, 1 staged in LDS */
     /* polymer */
     int32_t n_beads;        /* 2..128                                          */

@@ -148,13 +148,13 @@ try {
             layouts = {MUCA_LAYOUT_BIT, MUCA_LAYOUT_BYTE};
         for (int lay : layouts)
             for (int lpc : {1, 2, 4, 16})
-                for (int threads : {64, 256})
+                for (int threads : {64, 256, 512})
                     for (int tl : {0, 1}) {
                         muca_config c = *cfg;
                         c.layout = lay;
                         c.lanes_per_chain = lpc;
                         c.chains_per_block = threads / lpc > 0 ? threads / lpc : 1;
-                        if (c.chains_per_block * lpc != threads)
+                        if (c.chains_per_block * lpc != threads || (threads > 256 && tl == 0))
                             continue;
                         c.table_in_lds = tl;
                         cands.push_back(c);

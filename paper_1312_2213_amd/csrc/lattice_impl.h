@@ -1319,22 +1319,36 @@ __global__ __launch_bounds__(256) void lattice_sweeps(LatticeArgs a)
     sweep_block<MODEL, L, LAYOUT, TLDS, LPC>(a, (int)(blockIdx.x * (blockDim.x / LPC)), smem);
 }
 
+// The same with blocks of 512 threads and the table staged in LDS: where
+// the staged table leaves room for one block per CU, a block of 512 puts two
+// wavefronts on every SIMD, so that one wave's instructions fill the other's
+// wait for its threshold reads.  A kernel of its own, so that the register
+// budget of two waves per SIMD does not touch the 256-thread code.
+template <int MODEL, int L, int LAYOUT, int LPC>
+__global__ __launch_bounds__(512) void lattice_sweeps_wide(LatticeArgs a)
+{
+    extern __shared__ uint32_t smem[];
+    sweep_block<MODEL, L, LAYOUT, true, LPC>(a, (int)(blockIdx.x * (blockDim.x / LPC)), smem);
+}
+
 // ---------------------------------------------------------------------------
-// Launch of one compiled variant.  `threads` per block (64..256); LPC lanes
-// per chain, so a block holds threads / LPC chains.
+// Launch of one compiled variant.  `threads` per block (64..256, or 512
+// with the table in LDS); LPC lanes per chain, so a block holds
+// threads / LPC chains.
 // ---------------------------------------------------------------------------
 template <int MODEL, int L, int LAYOUT, int LPC>
 static hipError_t launch_variant(int threads, const LatticeArgs &a, hipStream_t s)
 {
     constexpr int NC = Cols<MODEL>::value;
     const long lanes = (long)a.c_pad * LPC;
-    if (threads < 64 || threads > 256 || lanes % threads)
+    const bool wide = threads == 512 && a.table_in_lds;
+    if (threads < 64 || (threads > 256 && !wide) || lanes % threads)
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)(lanes / threads)), block(threads);
     size_t lds = (size_t)lds_hist_words(a.n_bins) * 4u;
     if (a.table_in_lds) {
         lds += (size_t)a.n_bins * lds_table_cols(MODEL) * 4u;
-        auto k = lattice_sweeps<MODEL, L, LAYOUT, true, LPC>;
+        auto k = wide ? lattice_sweeps_wide<MODEL, L, LAYOUT, LPC> : lattice_sweeps<MODEL, L, LAYOUT, true, LPC>;
         if (lds > 65536u) {
             hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess)

@@ -151,10 +151,12 @@ int muca_geometry(const muca_config *c, Geometry *g)
         return muca_fail(MUCA_E_ARG, "lanes_per_chain %d not in {1, 2, 4, 16}", lpc);
     g->lpc = lpc;
     // default: 256-thread blocks, so a block that stages the threshold table
-    // in LDS (one block per CU) still carries four wavefronts of work
+    // in LDS (one block per CU) still carries four wavefronts of work; at
+    // init, 512 where that table leaves room for one block per CU and the
+    // launch fills every CU with such blocks
     int cpb = c->chains_per_block ? c->chains_per_block * lpc : 256;
-    if (c->chains_per_block && (c->chains_per_block < 1 || cpb > 256 || cpb % 64))
-        return muca_fail(MUCA_E_ARG, "chains_per_block %d x lanes_per_chain %d must be 64, 128 or 256 threads",
+    if (c->chains_per_block && (c->chains_per_block < 1 || cpb > 512 || cpb % 64 || (cpb & (cpb - 1))))
+        return muca_fail(MUCA_E_ARG, "chains_per_block %d x lanes_per_chain %d must be 64, 128, 256 or 512 threads",
                          c->chains_per_block, lpc);
     while (((long)g->c_pad * lpc) % cpb)
         cpb /= 2;
@@ -170,6 +172,8 @@ int muca_geometry(const muca_config *c, Geometry *g)
     if (hist_lds > 64u * 1024u)
         return muca_fail(MUCA_E_ARG, "%d bins exceed the LDS histogram", g->n_bins);
     g->table_in_lds = c->table_in_lds == 1 || (c->table_in_lds < 0 && g->lds_bytes <= 160u * 1024u);
+    if (g->cpb > 256 && !g->table_in_lds)
+        return muca_fail(MUCA_E_ARG, "blocks of %d threads need the threshold table staged in LDS", g->cpb);
     // workspace carve
     size_t off = 0;
     g->off_words = off;
@@ -309,10 +313,24 @@ try {
             hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
             const size_t need = g.lds_bytes;
             if (need > (size_t)lim) {
-                if (c->table_in_lds == 1)
+                if (c->table_in_lds == 1 || g.cpb > 256)
                     return muca_fail(MUCA_E_ARG, "LDS request of %zu bytes above the device limit %d", need, lim);
                 g.table_in_lds = false;
             }
+        }
+    }
+    if (g.model != kPolymer && c->chains_per_block == 0 && g.table_in_lds) {
+        // a staged table too large for two blocks of 256 per CU leaves one
+        // wavefront per SIMD; a block of 512 puts two there, once the launch
+        // has such a block for every CU
+        int dev = 0, cus = 0, lds_cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess) {
+            const long lanes = (long)g.c_pad * g.lpc;
+            if (2 * g.lds_bytes > (size_t)lds_cu && g.lds_bytes <= (size_t)lds_cu && cus > 0 &&
+                lanes >= 512L * cus && lanes % 512 == 0)
+                g.cpb = 512;
         }
     }
     RoctxRange range("muca_init");

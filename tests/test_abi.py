@@ -63,3 +63,18 @@ def test_host_only_calls_without_gpu():
     old = muca.muca_config_default("ising", 8, 2, 16, 1, abi_version=1)
     with pytest.raises(muca.MucaError):
         muca.muca_workspace_bytes(old)
+
+
+def test_block_shapes_checked_on_the_host():
+    """Blocks of 64 .. 512 threads (a power of two); 512 only beside a
+    threshold table staged in LDS."""
+    from paper_1312_2213_amd import muca
+    for lpc, cpb, tlds, ok in ((16, 4, -1, True), (16, 32, 1, True), (4, 128, -1, True), (1, 512, 1, True),
+                               (16, 32, 0, False), (16, 64, 1, False), (4, 48, 1, False), (1, 1024, 1, False)):
+        c = muca.muca_config_default("ising", 64, 2, 8192, 2, lanes_per_chain=lpc, chains_per_block=cpb,
+                                     table_in_lds=tlds)
+        if ok:
+            assert muca.muca_workspace_bytes(c) > 0
+        else:
+            with pytest.raises(muca.MucaError):
+                muca.muca_workspace_bytes(c)

@@ -50,12 +50,14 @@ def oracle_result(model, L, q, chains, seed):
     return _ORACLE[key]
 
 
-def run_variant(model, L, q, chains, seed, layout, lpc, tlds):
+def run_variant(model, L, q, chains, seed, layout, lpc, tlds, threads=0):
     from paper_1312_2213_amd import muca
-    kw = dict(layout=layout, lanes_per_chain=lpc, table_in_lds=tlds)
+    kw = dict(layout=layout, lanes_per_chain=lpc, table_in_lds=tlds, chains_per_block=threads // lpc)
     if model == "muma":
         kw["beta"] = 0.5
     g = muca.Run(muca.muca_config_default(model, L, q, chains, seed, **kw))
+    if threads:
+        assert g.blocks_shape()[1] * lpc == threads
     lnw, T, H, acc, spins, bins = oracle_result(model, L, q, chains, seed)
     g.set_lnw(lnw)
     assert np.array_equal(g.thresholds(), T), "threshold tables differ"
@@ -95,3 +97,40 @@ def test_muma_full_size_rejecting_weights(L, layout, lpc, tlds):
 def test_potts8_L48_full_size_rejecting_weights(lpc, tlds):
     print(f"potts q=8 L=48 chains=2048 lpc={lpc} tlds={tlds}", flush=True)
     run_variant("potts", 48, 8, 2048, 33, 0, lpc, tlds)
+
+
+@pytest.mark.parametrize("lpc", [16, 4])
+def test_ising64_512_thread_blocks_rejecting_weights(lpc):
+    """Blocks of 512 threads beside the staged table (two wavefronts per
+    SIMD) at 8192 chains: the oracle's chains, bit for bit."""
+    print(f"ising L=64 chains=8192 lpc={lpc} threads=512", flush=True)
+    run_variant("ising", 64, 2, 8192, 5, 1, lpc, 1, threads=512)
+
+
+def test_potts8_L48_512_thread_blocks_rejecting_weights():
+    print("potts q=8 L=48 chains=4096 lpc=16 threads=512", flush=True)
+    run_variant("potts", 48, 8, 4096, 35, 0, 16, 1, threads=512)
+
+
+def test_default_block_shape_with_many_chains():
+    """32768 chains of Ising L = 64 at 4 lanes per chain: by default the
+    library takes blocks of 512 threads (the staged table leaves room for
+    one block per CU, and the launch has one for every CU), and its chains
+    are those of 256-thread blocks at the same weights."""
+    from paper_1312_2213_amd import muca
+    C, L = 32768, 64
+    out = []
+    for cpb in (0, 64):
+        g = muca.Run(muca.muca_config_default("ising", L, 2, C, 7, layout=1, lanes_per_chain=4,
+                                              chains_per_block=cpb))
+        out.append(g.blocks_shape()[1] * 4)
+        g.set_lnw(weights("ising", L, g.cfg.lo, g.cfg.hi))
+        g.run_iteration(SWEEPS)
+        st = g.merge_update()
+        s, b, _ = g.chain_state(0, 4096)
+        out.append((g.last_hist(), st["accept_rate"], s, b))
+        g.free()
+    assert out[0] == 512 and out[2] == 256
+    (h0, a0, s0, b0), (h1, a1, s1, b1) = out[1], out[3]
+    assert np.array_equal(h0, h1) and a0 == a1 and 0.05 < a0 < 0.95
+    assert np.array_equal(s0, s1) and np.array_equal(b0, b1)

@@ -104,8 +104,8 @@ def test_invariant_to_launch_shape_lanes_and_table_placement(model, layout, q):
     o, _ = pair(model, 16, 128, seed=4, q=q, layout=layout)
     H = o.sweeps(25)
     for lpc in (1, 2, 4, 16):
-        for threads in (64, 256):
-            for tlds in (0, 1):
+        for threads in (64, 256, 512):
+            for tlds in ((0, 1) if threads <= 256 else (1,)):
                 cpb = max(1, threads // lpc)
                 _, g = pair(model, 16, 128, seed=4, q=q, layout=layout, cpb=cpb, tlds=tlds, lpc=lpc)
                 g.run_iteration(25)
@@ -215,18 +215,21 @@ def test_potts48_full_size_table_placement(tlds):
     assert_same_state(o, g, chains=(0, 777, 2047))
 
 
+@pytest.mark.parametrize("cpb", [256, 512])
 @pytest.mark.parametrize("model,q", [("ising", 2), ("potts", 3)])
-def test_lds_counters_flushed_before_16_bit_overflow(model, q):
-    """256 chains per block, 2000 sweeps in one launch: with W = 1 every
-    Ising flip is accepted, a sweep maps s -> -s and each chain keeps its
-    energy, so one bin collects far more than 2^16 counts per block.  The
-    packed 16-bit LDS counters must be flushed in time (every 255 sweeps)."""
-    print(f"{model} flush", flush=True)
-    o, g = pair(model, 4, 256, seed=21, q=q, lpc=1, cpb=256)
+def test_lds_counters_flushed_before_16_bit_overflow(model, q, cpb):
+    """256 or 512 chains per block, 2000 sweeps in one launch: with W = 1
+    every Ising flip is accepted, a sweep maps s -> -s and each chain keeps
+    its energy, so one bin collects far more than 2^16 counts per block.
+    The packed 16-bit LDS counters must be flushed in time (every
+    65535 / cpb sweeps)."""
+    print(f"{model} flush cpb={cpb}", flush=True)
+    o, g = pair(model, 4, cpb, seed=21, q=q, lpc=1, cpb=cpb, tlds=1)
+    assert g.blocks_shape()[1] == cpb
     H, _ = iterate_both(o, g, 2000, 2)
     assert_same_state(o, g)
     if model == "ising":
-        o2, g2 = pair(model, 4, 256, seed=21, lpc=1, cpb=256)
+        o2, g2 = pair(model, 4, cpb, seed=21, lpc=1, cpb=cpb, tlds=1)
         g2.run_iteration(2000)
         g2.merge_update()
         assert g2.last_hist().max() > 65535
