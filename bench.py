@@ -11,6 +11,8 @@ region.  The line also carries:
   roofline      the sweep kernel's figures (HIP-event duration on its stream;
                 HBM traffic from the rocprofv3 counters of the same kernel
                 sources, null once those sources have changed);
+  more_chains   the same kernel at 131072 chains (one lane per chain,
+                blocks of 512 threads: two wavefronts per SIMD), one launch;
   cpu_baseline  the single-threaded C oracle on a bounded sample of the same
                 workload at weights that reject moves, on one core and as one
                 process per core over disjoint chain ranges;
@@ -480,12 +482,41 @@ def bench_ising64(args):
         "iterations": [{k: s[k] for k in ("iteration", "flatness", "lo_visited", "hi_visited")}
                        for s in stats],
     }
+    if C == 4096 and S == 10000:
+        out["more_chains"] = more_chains(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     if not args.no_batched:
         out["time_to_flat"] = batched_vs_plain(None, max_iters=args.flat_max_iters,
                                                batch_lpc=args.batch_lanes_per_chain)
     return out
+
+
+def more_chains(stream, C=131072, S=1000):
+    """The headline kernel's model and size (Ising L = 64, bit layout, table
+    staged in LDS) with enough chains to keep two wavefronts on every SIMD:
+    131072 chains in the library's default shape for that count (one lane
+    per chain, blocks of 512 threads), one timed launch of S sweeps after an untimed one, at
+    the weights of the first merge."""
+    import torch
+    from paper_1312_2213_amd import muca
+    L = 64
+    run = muca.Run(muca.muca_config_default("ising", L, 2, C, 2, layout=muca.MUCA_LAYOUT_BIT, lanes_per_chain=1),
+                   stream=stream)
+    run.run_iteration(S // 10)
+    run.merge_update()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    run.run_iteration(S)
+    e1.record(stream)
+    st = run.merge_update()
+    ms = e0.elapsed_time(e1)
+    _, cpb = run.blocks_shape()
+    rate = C * L * L * S / (ms * 1e-3)
+    run.free()
+    return {"chains": C, "sweeps": S, "lanes_per_chain": 1, "threads_per_block": cpb, "kernel_ms": ms,
+            "attempts_per_s": rate, "frac_alu": rate * OPS_PER_ATTEMPT / PEAK_INT_OPS,
+            "accept_rate": st["accept_rate"]}
 
 
 def bench_potts48(args):
