@@ -99,12 +99,18 @@ def test_potts8_L48_full_size_rejecting_weights(lpc, tlds):
     run_variant("potts", 48, 8, 2048, 33, 0, lpc, tlds)
 
 
-@pytest.mark.parametrize("lpc", [16, 4])
+@pytest.mark.parametrize("lpc", [16, 4, 2, 1])
 def test_ising64_512_thread_blocks_rejecting_weights(lpc):
     """Blocks of 512 threads beside the staged table (two wavefronts per
     SIMD) at 8192 chains: the oracle's chains, bit for bit."""
     print(f"ising L=64 chains=8192 lpc={lpc} threads=512", flush=True)
     run_variant("ising", 64, 2, 8192, 5, 1, lpc, 1, threads=512)
+
+
+@pytest.mark.parametrize("lpc", [4, 1])
+def test_muma48_512_thread_blocks_rejecting_weights(lpc):
+    print(f"muma L=48 chains=4096 lpc={lpc} threads=512", flush=True)
+    run_variant("muma", 48, 2, 4096, 34, 1, lpc, 1, threads=512)
 
 
 def test_potts8_L48_512_thread_blocks_rejecting_weights():
