@@ -1339,7 +1339,6 @@ __global__ __launch_bounds__(512) void lattice_sweeps_wide(LatticeArgs a)
 template <int MODEL, int L, int LAYOUT, int LPC>
 static hipError_t launch_variant(int threads, const LatticeArgs &a, hipStream_t s)
 {
-    constexpr int NC = Cols<MODEL>::value;
     const long lanes = (long)a.c_pad * LPC;
     const bool wide = threads == 512 && a.table_in_lds;
     if (threads < 64 || (threads > 256 && !wide) || lanes % threads)
