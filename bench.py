@@ -188,7 +188,12 @@ def cpu_baseline(seconds: float) -> dict:
                                     f"{all_attempts:.3g} attempts in {all_dt:.1f} s"}}
 
 
-def batched_instances():
+def batched_instances(tune_layout: bool = True):
+    """The batched workload's instances as (config, sweeps per iteration).
+    The multimagnetic runs take the spin layout (bit or byte) that the
+    plain-launch autotuner measures fastest for their shape (one lattice
+    layout per run: its spins live in it); the batched launch then tunes
+    lanes per chain and table placement per run.  Potts has one layout."""
     from paper_1312_2213_amd import muca
     from synth import WORKLOADS, sweeps_per_iteration
     out = []
@@ -198,8 +203,9 @@ def batched_instances():
             sw = sweeps_per_iteration(inst["L"], inst["chains"], True)
         else:
             cfg = muca.muca_config_default("muma", inst["L"], 2, inst["chains"], inst["seed"],
-                                           beta=inst["beta"], layout=muca.MUCA_LAYOUT_BYTE)
+                                           beta=inst["beta"], layout=muca.MUCA_LAYOUT_AUTO)
             sw = sweeps_per_iteration(inst["L"], inst["chains"], False)
+            cfg.layout = muca.muca_autotune(cfg, sw)[0].layout if tune_layout else muca.MUCA_LAYOUT_BYTE
         out.append((cfg, sw))
     return out
 
@@ -347,7 +353,9 @@ def batched_vs_plain(rounds: int, max_iters: int | None = None, batch_lpc: int =
            "makespan_s": {"batched": tb, "served": ts, "plain": tp},
            "speedup_makespan": {"batched": tp / tb, "served": tp / ts},
            "attempts_per_s": {"batched": attempts / tb, "served": attempts / ts, "plain": attempts / tp},
-           "autotuned": bool(autotune and batch_lpc == 0), "tuned_vs_rule": tuned}
+           "autotuned": bool(autotune and batch_lpc == 0), "tuned_vs_rule": tuned,
+           "layouts": ["byte" if (c.model == muca.MUCA_POTTS or c.layout == muca.MUCA_LAYOUT_BYTE) else "bit"
+                       for c, _ in specs]}
     if max_iters is not None:
         out.update({"flat_threshold": 0.5, "max_iters": max_iters, "flat": run_batched.flat,
                     "mean_time_to_flat_s": {"batched": mean(ttf_b), "served": mean(ttf_s), "plain": mean(ttf_p)},
