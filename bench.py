@@ -21,7 +21,9 @@ region.  The line also carries:
                 instance run to a flat histogram (min/mean > 0.5): makespan
                 and mean time to flat of one persistent hipGraph launch per
                 round (batched), of the serving loop (served), and of the
-                instances one after another with plain launches (plain).
+                instances one after another with plain launches (plain);
+                the multimagnetic runs' spin layout from the plain-launch
+                autotuner (layouts).
 
 Other modes (--workload): "ising64_flat" (the headline configuration run to
 a flat histogram: time to flat), "potts48" (plain MUCA of the batched
